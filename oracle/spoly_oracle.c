@@ -1,0 +1,971 @@
+/*
+ * spoly_oracle.c -- plain, slow FP64 CPU oracle of the specular-polynomial
+ * solver (Fan et al., "Specular Polynomials", ACM TOG 43(4), 2024).
+ *
+ * TEST INFRASTRUCTURE.  Only the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark load this library.  It shares no code,
+ * header, table or helper with the HIP path; the two are compared on the same
+ * seeded inputs.
+ *
+ * What it computes, in the paper's order (Sec. 4 then Sec. 5):
+ *   coefficient phase  -- bivariate a(u,v), b(u,v) from the vertex constraints
+ *                         (coplanarity Eq. eq_coplane; product form Eq.
+ *                         eq_pf_result for R; square form Eq. eq_cpf_result
+ *                         for T) and, for two bounces, the rational coordinate
+ *                         mapping Eq. eq_rct with the refracted direction
+ *                         Eq. eq_refr_rational and the piecewise rational
+ *                         square-root approximation (Sec. 4.4);
+ *   elimination phase  -- Bezout matrix Eq. eq_bezout (Sec. 5.1); for one bounce
+ *                         its determinant is expanded by Laplace expansion into
+ *                         explicit coefficients of r(v) (Sec. 5.2);
+ *   univariate solve   -- one bounce: recursive derivative isolation plus
+ *                         bisection on each monotone piece (Sec. 5.2); two
+ *                         bounces: sign of det R(v) by Gaussian elimination at
+ *                         `pieces`+1 uniform points of [0,1] and `bisect_iters`
+ *                         bisection steps on every sign change (Sec. 5.2);
+ *   path phase         -- u from a(u)|_v (Sec. 5.3), FP64 Newton polish
+ *                         (Sec. 7, one Newton iteration fixes the refraction
+ *                         approximation), path-space check of h x n = 0
+ *                         (Eq. eq_ch) with side rules, inside-triangle test.
+ *
+ * Everything is double precision; nothing is blocked, fused or reordered
+ * beyond what those steps say.  Readings of points the paper leaves open are
+ * listed in the design notes and repeated at the place they apply.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_MAXSOL 16
+
+/* ------------------------------------------------------------------ params */
+typedef struct {
+    double tau;          /* path-space tolerance on |h^ x n^| (reading: 1e-6)          */
+    double u_margin;     /* u search interval [-m, 1-v+m] before polish                 */
+    double dedup;        /* solutions closer than this in (u,v) are one solution        */
+    int32_t polish_iters;/* max Newton iterations of the polish                         */
+    int32_t pieces;      /* uniform pieces of [0,1] for the >=2-bounce scan (100)       */
+    int32_t bisect_iters;/* bisection steps per sign change (10)                        */
+    int32_t pad;
+} or_params;
+
+typedef struct {
+    int32_t query;       /* instance index                                              */
+    int32_t flags;
+    double u1, v1, u2, v2;
+    double residual;     /* max over the chain of |h^ x n^|                             */
+    double edge;         /* min over the chain of min(u, v, 1-u-v)                      */
+} or_sol;
+
+typedef struct {
+    int32_t n_vroots;    /* roots of the univariate problem found in [0,1]              */
+    int32_t n_cand;      /* (u,v) candidates sent to polish                             */
+    int32_t n_valid;     /* reported solutions                                          */
+    int32_t flags;       /* OR_F_* below                                                */
+    double tangency;     /* min |r(c)|/max|r_k| over critical points c of r in [0,1]   */
+    double min_gap;      /* smallest gap between consecutive v roots (1 if < 2 roots)   */
+} or_diag;
+
+enum { OR_F_DEGENERATE = 1, OR_F_EDGE2 = 2, OR_F_AXIS_Z = 4, OR_F_AXIS_Y = 8,
+       OR_F_FLAT1 = 16, OR_F_FLAT2 = 32, OR_F_OVERFLOW = 64 };
+
+/* ------------------------------------------------------------------ arena */
+typedef struct { char *base; size_t cap, top; } arena;
+
+static void *ar_alloc(arena *A, size_t n)
+{
+    n = (n + 15) & ~(size_t)15;
+    if (A->top + n > A->cap) { fprintf(stderr, "oracle arena exhausted\n"); abort(); }
+    void *p = A->base + A->top;
+    A->top += n;
+    memset(p, 0, n);
+    return p;
+}
+
+/* ------------------------------------------------------------------ 3-vectors */
+typedef struct { double x, y, z; } v3;
+static v3 V(double x, double y, double z) { v3 r = {x, y, z}; return r; }
+static v3 vadd(v3 a, v3 b) { return V(a.x + b.x, a.y + b.y, a.z + b.z); }
+static v3 vsub(v3 a, v3 b) { return V(a.x - b.x, a.y - b.y, a.z - b.z); }
+static v3 vmul(v3 a, double s) { return V(a.x * s, a.y * s, a.z * s); }
+static double vdot(v3 a, v3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+static v3 vcross(v3 a, v3 b)
+{
+    return V(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+static double vlen(v3 a) { return sqrt(vdot(a, a)); }
+static v3 vnorm(v3 a) { double l = vlen(a); return l > 0 ? vmul(a, 1.0 / l) : a; }
+static v3 vload(const double *p, int64_t i) { return V(p[3 * i], p[3 * i + 1], p[3 * i + 2]); }
+
+/* ------------------------------------------------------------------ bivariate polynomials
+ * p(u,v) = sum_{i+j<=d} c[i*(d+1)+j] u^i v^j.  Degrees are tracked by
+ * construction (structure), never inferred from coefficient values.          */
+typedef struct { int d; double *c; } bp;
+
+static bp bp_new(arena *A, int d)
+{
+    bp p;
+    p.d = d < 0 ? 0 : d;
+    p.c = (double *)ar_alloc(A, sizeof(double) * (size_t)(p.d + 1) * (size_t)(p.d + 1));
+    return p;
+}
+static double bp_at(bp p, int i, int j)
+{
+    if (i < 0 || j < 0 || i + j > p.d) return 0.0;
+    return p.c[i * (p.d + 1) + j];
+}
+static bp bp_const(arena *A, double k) { bp p = bp_new(A, 0); p.c[0] = k; return p; }
+static bp bp_lin(arena *A, double k0, double ku, double kv)
+{
+    bp p = bp_new(A, 1);
+    p.c[0] = k0;          /* u^0 v^0 */
+    p.c[1] = kv;          /* u^0 v^1 */
+    p.c[2] = ku;          /* u^1 v^0 */
+    return p;
+}
+static bp bp_mul(arena *A, bp a, bp b)
+{
+    bp r = bp_new(A, a.d + b.d);
+    for (int i = 0; i <= a.d; ++i)
+        for (int j = 0; i + j <= a.d; ++j) {
+            double x = a.c[i * (a.d + 1) + j];
+            if (x == 0.0) continue;
+            for (int k = 0; k <= b.d; ++k)
+                for (int l = 0; k + l <= b.d; ++l)
+                    r.c[(i + k) * (r.d + 1) + (j + l)] += x * b.c[k * (b.d + 1) + l];
+        }
+    return r;
+}
+/* sa*a + sb*b */
+static bp bp_lc(arena *A, double sa, bp a, double sb, bp b)
+{
+    bp r = bp_new(A, a.d > b.d ? a.d : b.d);
+    for (int i = 0; i <= r.d; ++i)
+        for (int j = 0; i + j <= r.d; ++j)
+            r.c[i * (r.d + 1) + j] = sa * bp_at(a, i, j) + sb * bp_at(b, i, j);
+    return r;
+}
+static bp bp_add(arena *A, bp a, bp b) { return bp_lc(A, 1.0, a, 1.0, b); }
+static bp bp_sub(arena *A, bp a, bp b) { return bp_lc(A, 1.0, a, -1.0, b); }
+static bp bp_scale(arena *A, bp a, double s) { return bp_lc(A, s, a, 0.0, a); }
+
+/* value and partial derivatives at (u,v), by direct summation */
+static void bp_eval3(bp p, double u, double v, double *f, double *fu, double *fv)
+{
+    double s = 0, su = 0, sv = 0;
+    for (int i = 0; i <= p.d; ++i)
+        for (int j = 0; i + j <= p.d; ++j) {
+            double c = p.c[i * (p.d + 1) + j];
+            s += c * pow(u, i) * pow(v, j);
+            if (i > 0) su += c * i * pow(u, i - 1) * pow(v, j);
+            if (j > 0) sv += c * j * pow(u, i) * pow(v, j - 1);
+        }
+    *f = s; if (fu) *fu = su; if (fv) *fv = sv;
+}
+
+/* vectors of bivariate polynomials */
+typedef struct { bp x, y, z; } bv;
+static bv bv_affine(arena *A, v3 p0, v3 eu, v3 ev)     /* p0 + u eu + v ev */
+{
+    bv r;
+    r.x = bp_lin(A, p0.x, eu.x, ev.x);
+    r.y = bp_lin(A, p0.y, eu.y, ev.y);
+    r.z = bp_lin(A, p0.z, eu.z, ev.z);
+    return r;
+}
+static bv bv_const(arena *A, v3 c)
+{
+    bv r; r.x = bp_const(A, c.x); r.y = bp_const(A, c.y); r.z = bp_const(A, c.z); return r;
+}
+static bv bv_add(arena *A, bv a, bv b) { bv r = {bp_add(A, a.x, b.x), bp_add(A, a.y, b.y), bp_add(A, a.z, b.z)}; return r; }
+static bv bv_sub(arena *A, bv a, bv b) { bv r = {bp_sub(A, a.x, b.x), bp_sub(A, a.y, b.y), bp_sub(A, a.z, b.z)}; return r; }
+static bv bv_smul(arena *A, bp s, bv a) { bv r = {bp_mul(A, s, a.x), bp_mul(A, s, a.y), bp_mul(A, s, a.z)}; return r; }
+static bv bv_kmul(arena *A, double k, bv a) { bv r = {bp_scale(A, a.x, k), bp_scale(A, a.y, k), bp_scale(A, a.z, k)}; return r; }
+static bv bv_vmul(arena *A, bp s, v3 c)   /* s * constant vector */
+{
+    bv r = {bp_scale(A, s, c.x), bp_scale(A, s, c.y), bp_scale(A, s, c.z)}; return r;
+}
+static bp bv_dot(arena *A, bv a, bv b)
+{
+    return bp_add(A, bp_add(A, bp_mul(A, a.x, b.x), bp_mul(A, a.y, b.y)), bp_mul(A, a.z, b.z));
+}
+static bp bv_dotc(arena *A, bv a, v3 c)
+{
+    return bp_add(A, bp_add(A, bp_scale(A, a.x, c.x), bp_scale(A, a.y, c.y)), bp_scale(A, a.z, c.z));
+}
+static bv bv_cross(arena *A, bv a, bv b)
+{
+    bv r;
+    r.x = bp_sub(A, bp_mul(A, a.y, b.z), bp_mul(A, a.z, b.y));
+    r.y = bp_sub(A, bp_mul(A, a.z, b.x), bp_mul(A, a.x, b.z));
+    r.z = bp_sub(A, bp_mul(A, a.x, b.y), bp_mul(A, a.y, b.x));
+    return r;
+}
+
+/* ------------------------------------------------------------------ univariate polynomials in v */
+typedef struct { int d; double *c; } up;   /* sum_{k<=d} c[k] v^k ; d < 0 means the zero polynomial */
+
+static up up_new(arena *A, int d)
+{
+    up p; p.d = d;
+    p.c = (double *)ar_alloc(A, sizeof(double) * (size_t)(d < 0 ? 1 : d + 1));
+    return p;
+}
+static up up_mul(arena *A, up a, up b)
+{
+    if (a.d < 0 || b.d < 0) return up_new(A, -1);
+    up r = up_new(A, a.d + b.d);
+    for (int i = 0; i <= a.d; ++i)
+        for (int j = 0; j <= b.d; ++j) r.c[i + j] += a.c[i] * b.c[j];
+    return r;
+}
+static up up_lc(arena *A, double sa, up a, double sb, up b)
+{
+    int d = a.d > b.d ? a.d : b.d;
+    up r = up_new(A, d);
+    for (int k = 0; k <= d; ++k)
+        r.c[k] = (k <= a.d ? sa * a.c[k] : 0.0) + (k <= b.d ? sb * b.c[k] : 0.0);
+    return r;
+}
+static double up_eval(const double *c, int d, double v)
+{
+    double s = 0.0;
+    for (int k = d; k >= 0; --k) s = s * v + c[k];
+    return s;
+}
+/* coefficient of u^i in p(u,v), as a polynomial in v of degree p.d - i */
+static up bp_ucoef(arena *A, bp p, int i)
+{
+    if (i > p.d) return up_new(A, -1);
+    up r = up_new(A, p.d - i);
+    for (int j = 0; j <= p.d - i; ++j) r.c[j] = p.c[i * (p.d + 1) + j];
+    return r;
+}
+
+/* ------------------------------------------------------------------ Bezout resultant, Eq. (eq_bezout)
+ * (i,j) entry, 0 <= i,j < n:
+ *     sum_{k=0}^{min(i, n-1-j)} a_{i-k} b_{j+1+k} - b_{i-k} a_{j+1+k}
+ * with a_m = b_m = 0 beyond the polynomial's u-degree.  n is the structural
+ * u-degree of the system (never inferred from values).                      */
+static void bezout_poly(arena *A, const up *ac, const up *bc, int n, up *M /* n*n */)
+{
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            up s = up_new(A, -1);
+            int kmax = i < n - 1 - j ? i : n - 1 - j;
+            for (int k = 0; k <= kmax; ++k) {
+                up t1 = up_mul(A, ac[i - k], bc[j + 1 + k]);
+                up t2 = up_mul(A, bc[i - k], ac[j + 1 + k]);
+                s = up_lc(A, 1.0, s, 1.0, up_lc(A, 1.0, t1, -1.0, t2));
+            }
+            M[i * n + j] = s;
+        }
+}
+
+/* Laplace (cofactor) expansion along the first remaining row, Sec. 5.2.
+ * Rows r..n-1, columns given by `mask`.                                      */
+static up laplace(arena *A, const up *M, int n, int r, unsigned mask)
+{
+    if (r == n) { up one = up_new(A, 0); one.c[0] = 1.0; return one; }
+    up acc = up_new(A, -1);
+    int pos = 0;
+    for (int j = 0; j < n; ++j) {
+        if (!(mask & (1u << j))) continue;
+        up e = M[r * n + j];
+        if (e.d >= 0) {
+            up minor = laplace(A, M, n, r + 1, mask & ~(1u << j));
+            up t = up_mul(A, e, minor);
+            acc = up_lc(A, 1.0, acc, (pos & 1) ? -1.0 : 1.0, t);
+        }
+        ++pos;
+    }
+    return acc;
+}
+
+/* ------------------------------------------------------------------ univariate root isolation (Sec. 5.2)
+ * The zeros of p' split [lo,hi] into monotone pieces; a piece whose end values
+ * have strictly different signs holds exactly one root, found by bisection.
+ * Reading: sgn(0) := +1.  The oracle bisects until the interval stops
+ * shrinking (full double precision), which is finer than the paper's 1e-9.   */
+static int sgn(double x) { return x < 0.0 ? -1 : 1; }
+
+static double bisect_full(const double *c, int d, double l, double r, int sl)
+{
+    for (int it = 0; it < 2000; ++it) {
+        double m = 0.5 * (l + r);
+        if (!(m > l && m < r)) break;
+        if (sgn(up_eval(c, d, m)) == sl) l = m; else r = m;
+    }
+    return 0.5 * (l + r);
+}
+
+/* roots of sum c[k] x^k (degree d) in [lo,hi]; returns count, ascending */
+static int isolate(arena *A, const double *c, int d, double lo, double hi, double *roots, int cap)
+{
+    double *crit = NULL;
+    int nc = 0;
+    if (d >= 2) {
+        double *dc = (double *)ar_alloc(A, sizeof(double) * (size_t)d);
+        for (int k = 1; k <= d; ++k) dc[k - 1] = k * c[k];
+        crit = (double *)ar_alloc(A, sizeof(double) * (size_t)d);
+        nc = isolate(A, dc, d - 1, lo, hi, crit, d);
+    }
+    int nr = 0;
+    double l = lo, fl = up_eval(c, d, lo);
+    for (int k = 0; k <= nc; ++k) {
+        double r = (k < nc) ? crit[k] : hi;
+        double fr = up_eval(c, d, r);
+        if (r > l && sgn(fl) != sgn(fr)) {
+            double x = bisect_full(c, d, l, r, sgn(fl));
+            if (nr == 0 || x - roots[nr - 1] > 1e-12) {
+                if (nr < cap) roots[nr++] = x;
+            }
+        }
+        l = r; fl = fr;
+    }
+    return nr;
+}
+
+/* ------------------------------------------------------------------ path-space check (Eq. eq_ch)
+ * Reading of the check the paper delegates to prior work: with
+ * wi = normalize(x_prev - x), wo = normalize(x_next - x),
+ * h = eta_in wi + eta_out wo (the generalised half vector of Eq. eq_ch up to sign),
+ * a vertex is admissible iff |h^ x n^| <= tau and (wi.n)(wo.n) > 0 for
+ * reflection, < 0 for refraction.                                             */
+static int vertex_law(v3 xp, v3 x, v3 xn, v3 nrm, double eta_in, double eta_out, int refract, double *res)
+{
+    double ln = vlen(nrm);
+    if (!(ln > 1e-12)) { *res = 1e300; return 0; }
+    v3 nh = vmul(nrm, 1.0 / ln);
+    v3 wi = vnorm(vsub(xp, x)), wo = vnorm(vsub(xn, x));
+    v3 h = vadd(vmul(wi, eta_in), vmul(wo, eta_out));
+    double lh = vlen(h);
+    if (!(lh > 0)) { *res = 1e300; return 0; }
+    double r = vlen(vcross(vmul(h, 1.0 / lh), nh));
+    *res = r;
+    double side = vdot(wi, nh) * vdot(wo, nh);
+    int ok_side = refract ? (side < 0.0) : (side > 0.0);
+    return ok_side;
+}
+
+static double edge_dist(double u, double v)
+{
+    double w = 1.0 - u - v, m = u < v ? u : v;
+    return m < w ? m : w;
+}
+
+static int bary_inside(double u, double v) { return u >= 0.0 && v >= 0.0 && u + v <= 1.0; }
+
+/* ------------------------------------------------------------------ axis / tangent rules
+ * Square form (Eq. eq_cpf_result): b = x^ by default, another axis when the
+ * projection degenerates.  On the coplanarity curve both sides of Eq.
+ * eq_angrel2 are parallel to the incidence-plane normal m, so the projection
+ * degenerates where m.b -> 0.  Reading: with m_c = normalize((c - xa) x (xb - xa))
+ * at the triangle centroid c, take x^ if |m_c.x^| >= 1/2, else z^ if
+ * |m_c.z^| >= 1/2, else y^.
+ * Product form (Eq. eq_pf_result): t = n x e1 by default; along the
+ * coplanarity curve d.t = (e1.m)(d.(n x m)), so it degenerates when e1 lies in
+ * the incidence plane.  Reading: switch to t = n x e2 iff |e1^.m_c| < 1/4 and
+ * |e2^.m_c| > |e1^.m_c|.                                                       */
+static int pick_axis(v3 c, v3 xa, v3 xb, v3 *axis)
+{
+    v3 m = vcross(vsub(c, xa), vsub(xb, xa));
+    double l = vlen(m);
+    if (!(l > 0)) { *axis = V(1, 0, 0); return 0; }
+    m = vmul(m, 1.0 / l);
+    if (fabs(m.x) >= 0.5) { *axis = V(1, 0, 0); return 0; }
+    if (fabs(m.z) >= 0.5) { *axis = V(0, 0, 1); return OR_F_AXIS_Z; }
+    *axis = V(0, 1, 0);
+    return OR_F_AXIS_Y;
+}
+
+static int pick_edge2(v3 c, v3 xa, v3 xb, v3 e1, v3 e2)
+{
+    v3 m = vcross(vsub(c, xa), vsub(xb, xa));
+    double l = vlen(m);
+    if (!(l > 0)) return 0;
+    m = vmul(m, 1.0 / l);
+    double g1 = fabs(vdot(vnorm(e1), m)), g2 = fabs(vdot(vnorm(e2), m));
+    return (g1 < 0.25 && g2 > g1) ? 1 : 0;
+}
+
+/* ------------------------------------------------------------------ one bounce: coefficient phase
+ * R  (Sec. 4.5):  a = ((P u - x0) x (x2 - x0)) . N u                       (Eq. eq_coplane)
+ *                 b = ((Pu-x0).Nu)((x2-Pu).t) + ((x2-Pu).Nu)((Pu-x0).t),
+ *                     t = N u x e                                          (Eq. eq_pf_result)
+ * T  (Sec. 4.5):  b = eta0^2 |x2-Pu|^2 (((Pu-x0) x Nu).b)^2
+ *                   - eta1^2 |Pu-x0|^2 (((x2-Pu) x Nu).b)^2                 (Eq. eq_cpf_result)
+ * Returns the structural u-degree of b (the Bezout size n).                 */
+typedef struct { v3 p0, e1, e2, n0, dn1, dn2; int flat; } tri_t;
+
+static tri_t load_tri(const double *P, const double *N, const int32_t *tri, int64_t t)
+{
+    tri_t T;
+    int32_t i0 = tri[3 * t], i1 = tri[3 * t + 1], i2 = tri[3 * t + 2];
+    v3 p0 = vload(P, i0), p1 = vload(P, i1), p2 = vload(P, i2);
+    v3 n0 = vload(N, i0), n1 = vload(N, i1), n2 = vload(N, i2);
+    T.p0 = p0; T.e1 = vsub(p1, p0); T.e2 = vsub(p2, p0);
+    T.n0 = n0; T.dn1 = vsub(n1, n0); T.dn2 = vsub(n2, n0);
+    T.flat = (n0.x == n1.x && n0.y == n1.y && n0.z == n1.z && n0.x == n2.x && n0.y == n2.y && n0.z == n2.z);
+    return T;
+}
+static v3 tri_x(const tri_t *T, double u, double v) { return vadd(T->p0, vadd(vmul(T->e1, u), vmul(T->e2, v))); }
+static v3 tri_n(const tri_t *T, double u, double v) { return vadd(T->n0, vadd(vmul(T->dn1, u), vmul(T->dn2, v))); }
+
+static bv tri_xpoly(arena *A, const tri_t *T) { return bv_affine(A, T->p0, T->e1, T->e2); }
+static bv tri_npoly(arena *A, const tri_t *T)
+{
+    if (T->flat) return bv_const(A, T->n0);
+    return bv_affine(A, T->n0, T->dn1, T->dn2);
+}
+
+static int coeffs_1b(arena *A, const tri_t *T, v3 x0, v3 x2, int refract, double eta0, double eta1,
+                     bp *pa, bp *pb, int *flags)
+{
+    int f = T->flat ? 0 : 1;
+    bv x1 = tri_xpoly(A, T);
+    bv n = tri_npoly(A, T);
+    bv d0 = bv_sub(A, x1, bv_const(A, x0));         /* x1 - x0 */
+    bv d1 = bv_sub(A, bv_const(A, x2), x1);         /* x2 - x1 */
+    v3 w = vsub(x2, x0);
+    /* a: endpoint-difference coplanarity */
+    *pa = bv_dot(A, bv_cross(A, d0, bv_const(A, w)), n);
+    v3 c = tri_x(T, 1.0 / 3.0, 1.0 / 3.0);
+    if (!refract) {
+        int use2 = pick_edge2(c, x0, x2, T->e1, T->e2);
+        if (use2) *flags |= OR_F_EDGE2;
+        bv t = bv_cross(A, n, bv_const(A, use2 ? T->e2 : T->e1));
+        *pb = bp_add(A, bp_mul(A, bv_dot(A, d0, n), bv_dot(A, d1, t)),
+                        bp_mul(A, bv_dot(A, d0, t), bv_dot(A, d1, n)));
+        /* with t = n x e1 the u^(2+2f) term cancels: e1.(dn1 x e1) = 0 */
+        return use2 ? 2 + 2 * f : 1 + 2 * f;
+    } else {
+        v3 ax;
+        *flags |= pick_axis(c, x0, x2, &ax);
+        bp l = bv_dotc(A, bv_cross(A, d0, n), ax);
+        bp r = bv_dotc(A, bv_cross(A, d1, n), ax);
+        bp t1 = bp_mul(A, bv_dot(A, d1, d1), bp_mul(A, l, l));
+        bp t2 = bp_mul(A, bv_dot(A, d0, d0), bp_mul(A, r, r));
+        *pb = bp_lc(A, eta0 * eta0, t1, -eta1 * eta1, t2);
+        return 4 + 2 * f;
+    }
+}
+
+
+/* Numerical u-degree of p, at most `cap` (the structural degree).  A top row of
+ * u-powers is dropped when it is exactly zero or below 1e-10 times the row under
+ * it: exact algebraic cancellations of the input family (parallel flat
+ * triangles; sphere normals equal to position/radius) leave such rows as
+ * rounding residues, while the natural decay of the coefficients of a small
+ * triangle is orders of magnitude slower.  Dropped rows are set to zero.     */
+static double row_max(bp p, int i)
+{
+    double m = 0.0;
+    for (int j = 0; i + j <= p.d; ++j) m = fmax(m, fabs(p.c[i * (p.d + 1) + j]));
+    return m;
+}
+static int numeric_udeg(bp p, int cap)
+{
+    int d = cap < p.d ? cap : p.d;
+    while (d > 0) {
+        double top = row_max(p, d), below = row_max(p, d - 1);
+        if (top == 0.0 || top < 1e-10 * below) --d;
+        else break;
+    }
+    for (int i = d + 1; i <= p.d; ++i)
+        for (int j = 0; i + j <= p.d; ++j) p.c[i * (p.d + 1) + j] = 0.0;
+    return d;
+}
+
+/* FP64 Newton on the bivariate system (a,b) = 0 (Sec. 7 polish reading).
+ * Returns 1 if the last step was below 1e-10.                               */
+static int polish_ab(bp a, bp b, int iters, double *pu, double *pv)
+{
+    double u = *pu, v = *pv, step = 1e300;
+    for (int it = 0; it < iters; ++it) {
+        double fa, au, av, fb, bu, bvv;
+        bp_eval3(a, u, v, &fa, &au, &av);
+        bp_eval3(b, u, v, &fb, &bu, &bvv);
+        double det = au * bvv - av * bu;
+        if (!(det != 0.0) || !isfinite(det)) break;
+        double du = (fa * bvv - av * fb) / det;
+        double dv = (au * fb - fa * bu) / det;
+        u -= du; v -= dv;
+        step = fabs(du) + fabs(dv);
+        if (!(step > 1e-16)) break;
+    }
+    *pu = u; *pv = v;
+    return step <= 1e-10;
+}
+
+static int add_solution(or_sol *S, int n, double dedup, or_sol s)
+{
+    for (int k = 0; k < n; ++k)
+        if (fabs(S[k].u1 - s.u1) < dedup && fabs(S[k].v1 - s.v1) < dedup) return n;
+    if (n < OR_MAXSOL) S[n++] = s;
+    return n;
+}
+
+/* one (x0, x2, triangle) instance */
+static void solve_1b(arena *A, const tri_t *T, v3 x0, v3 x2, int refract, double eta0, double eta1,
+                     const or_params *prm, int32_t qid, or_sol *out, int32_t *nout, or_diag *dg)
+{
+    memset(dg, 0, sizeof(*dg));
+    dg->min_gap = 1.0;
+    dg->tangency = 1e300;
+    if (T->flat) dg->flags |= OR_F_FLAT1;
+    bp a, b;
+    int nb = coeffs_1b(A, T, x0, x2, refract, eta0, eta1, &a, &b, &dg->flags);
+    int ma = numeric_udeg(a, a.d);
+    nb = numeric_udeg(b, nb);
+    int n = ma > nb ? ma : nb;
+    if (n < 1) { dg->flags |= OR_F_DEGENERATE; *nout = 0; return; }
+    /* elimination: coefficient polynomials a_i(v), b_i(v), i = 0..n */
+    up *ac = (up *)ar_alloc(A, sizeof(up) * (size_t)(n + 1));
+    up *bc = (up *)ar_alloc(A, sizeof(up) * (size_t)(n + 1));
+    for (int i = 0; i <= n; ++i) { ac[i] = bp_ucoef(A, a, i); bc[i] = bp_ucoef(A, b, i); }
+    up *M = (up *)ar_alloc(A, sizeof(up) * (size_t)(n * n));
+    bezout_poly(A, ac, bc, n, M);
+    up r = laplace(A, M, n, 0, (1u << n) - 1u);
+    double scale = 0.0;
+    for (int k = 0; k <= r.d; ++k) scale = fmax(scale, fabs(r.c[k]));
+    int nsol = 0;
+    if (r.d < 0 || !(scale > 0.0) || !isfinite(scale)) {
+        dg->flags |= OR_F_DEGENERATE;
+        *nout = 0;
+        return;
+    }
+    /* tangency diagnostic at the critical points of r */
+    if (r.d >= 2) {
+        double *dc = (double *)ar_alloc(A, sizeof(double) * (size_t)r.d);
+        for (int k = 1; k <= r.d; ++k) dc[k - 1] = k * r.c[k];
+        double crit[64];
+        int ncr = isolate(A, dc, r.d - 1, 0.0, 1.0, crit, 64);
+        for (int k = 0; k < ncr; ++k)
+            dg->tangency = fmin(dg->tangency, fabs(up_eval(r.c, r.d, crit[k])) / scale);
+    }
+    double vr[64];
+    int nv = isolate(A, r.c, r.d, 0.0, 1.0, vr, 64);
+    dg->n_vroots = nv;
+    for (int k = 1; k < nv; ++k) dg->min_gap = fmin(dg->min_gap, vr[k] - vr[k - 1]);
+    for (int k = 0; k < nv; ++k) {
+        double v = vr[k];
+        /* path phase: u from a(u)|_v */
+        int da = ma;
+        double *auc = (double *)ar_alloc(A, sizeof(double) * (size_t)(da + 1));
+        for (int i = 0; i <= da; ++i) auc[i] = up_eval(ac[i].c, ac[i].d, v);
+        double ur[64];
+        int nu = isolate(A, auc, da, -prm->u_margin, 1.0 - v + prm->u_margin, ur, 64);
+        for (int m = 0; m < nu; ++m) {
+            double u = ur[m], vv = v;
+            dg->n_cand++;
+            if (!polish_ab(a, b, prm->polish_iters, &u, &vv)) continue;
+            if (!bary_inside(u, vv)) continue;
+            v3 x1 = tri_x(T, u, vv), nn = tri_n(T, u, vv);
+            double res;
+            if (!vertex_law(x0, x1, x2, nn, eta0, eta1, refract, &res)) continue;
+            if (!(res <= prm->tau)) continue;
+            or_sol s;
+            memset(&s, 0, sizeof(s));
+            s.query = qid; s.u1 = u; s.v1 = vv; s.u2 = 0; s.v2 = 0;
+            s.residual = res; s.edge = edge_dist(u, vv); s.flags = dg->flags;
+            nsol = add_solution(out, nsol, prm->dedup, s);
+        }
+    }
+    dg->n_valid = nsol;
+    *nout = nsol;
+}
+
+/* ------------------------------------------------------------------ exported: one bounce
+ * P,N: [nv*3] vertex positions / normals; tri: [nt*3]; x0s: [n0*3]; x2s: [n2*3];
+ * queries q_x0[q], q_x2[q], q_tri[q].  Output: out[q*OR_MAXSOL + k], k < count[q].  */
+int or_solve_1bounce(const double *P, const double *N, const int32_t *tri, int64_t nt,
+                     const double *x0s, const double *x2s,
+                     const int32_t *q_x0, const int32_t *q_x2, const int32_t *q_tri, int64_t nq,
+                     int32_t refract, double eta0, double eta1, const or_params *prm,
+                     or_sol *out, int32_t *count, or_diag *diag)
+{
+    (void)nt;
+    int bad = 0;
+#pragma omp parallel
+    {
+        arena A;
+        A.cap = (size_t)8 << 20; A.top = 0; A.base = (char *)malloc(A.cap);
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t q = 0; q < nq; ++q) {
+            A.top = 0;
+            tri_t T = load_tri(P, N, tri, q_tri[q]);
+            solve_1b(&A, &T, vload(x0s, q_x0[q]), vload(x2s, q_x2[q]), refract, eta0, eta1, prm,
+                     (int32_t)q, out + q * OR_MAXSOL, count + q, diag + q);
+        }
+        free(A.base);
+    }
+    return bad;
+}
+
+/* ------------------------------------------------------------------ exported helpers for the pin tests */
+
+/* bivariate coefficients of the one-bounce system, dense (d+1)^2 arrays  */
+int or_coeffs_1bounce(const double *P, const double *N, const int32_t *tri, int64_t t,
+                      const double *x0, const double *x2, int32_t refract, double eta0, double eta1,
+                      double *a_out, int32_t *da, double *b_out, int32_t *db, int32_t *n_bez, int32_t *flags)
+{
+    arena A; A.cap = (size_t)8 << 20; A.top = 0; A.base = (char *)malloc(A.cap);
+    tri_t T = load_tri(P, N, tri, t);
+    bp a, b; int fl = 0;
+    int nb = coeffs_1b(&A, &T, vload(x0, 0), vload(x2, 0), refract, eta0, eta1, &a, &b, &fl);
+    int ma = numeric_udeg(a, a.d);
+    nb = numeric_udeg(b, nb);
+    int n = ma > nb ? ma : nb;
+    *da = a.d; *db = b.d; *n_bez = n; *flags = fl;
+    memcpy(a_out, a.c, sizeof(double) * (size_t)(a.d + 1) * (size_t)(a.d + 1));
+    memcpy(b_out, b.c, sizeof(double) * (size_t)(b.d + 1) * (size_t)(b.d + 1));
+    free(A.base);
+    return 0;
+}
+
+/* Bezout + Laplace of given bivariate a, b (dense, degrees da, db) with Bezout size n.
+ * r_out receives the coefficients of r(v); returns its degree.  */
+int or_resultant_laplace(const double *a_in, int32_t da, const double *b_in, int32_t db, int32_t n, double *r_out)
+{
+    arena A; A.cap = (size_t)32 << 20; A.top = 0; A.base = (char *)malloc(A.cap);
+    bp a = bp_new(&A, da), b = bp_new(&A, db);
+    memcpy(a.c, a_in, sizeof(double) * (size_t)(da + 1) * (size_t)(da + 1));
+    memcpy(b.c, b_in, sizeof(double) * (size_t)(db + 1) * (size_t)(db + 1));
+    up *ac = (up *)ar_alloc(&A, sizeof(up) * (size_t)(n + 1));
+    up *bc = (up *)ar_alloc(&A, sizeof(up) * (size_t)(n + 1));
+    for (int i = 0; i <= n; ++i) { ac[i] = bp_ucoef(&A, a, i); bc[i] = bp_ucoef(&A, b, i); }
+    up *M = (up *)ar_alloc(&A, sizeof(up) * (size_t)(n * n));
+    bezout_poly(&A, ac, bc, n, M);
+    up r = laplace(&A, M, n, 0, (1u << n) - 1u);
+    for (int k = 0; k <= r.d; ++k) r_out[k] = r.c[k];
+    int d = r.d;
+    free(A.base);
+    return d;
+}
+
+/* real roots of sum c[k] x^k in [lo,hi] by the recursive isolation */
+int or_isolate(const double *c, int32_t d, double lo, double hi, double *roots, int32_t cap)
+{
+    arena A; A.cap = (size_t)8 << 20; A.top = 0; A.base = (char *)malloc(A.cap);
+    int n = isolate(&A, c, d, lo, hi, roots, cap);
+    free(A.base);
+    return n;
+}
+
+/* ================================================================== two bounces (TT)
+ * Chain x0 -> x1 on T1 -> x2 on T2 -> x3, refraction at both vertices, IORs
+ * eta[0] (segment x0x1), eta[1] (x1x2), eta[2] (x2x3).
+ *
+ * Coefficient phase:
+ *   d0 = x1 - x0, n1 = N1 u;  beta = n1^2 d0^2 - eta'^2 (n1^2 d0^2 - (d0.n1)^2),
+ *   eta' = eta0/eta1                                             (Eq. eq_refr_rational)
+ *   sqrt(beta) ~ sqrt(S) R_p(beta/S), R_p(s) = (c0 + c1 s)/(d0 + d1 s)   (Sec. 4.4)
+ *     reading: S = n1^2 d0^2 at the centroid of T1 (a per-tuple constant) and the
+ *     piece p is the one that holds beta/S at the centroid.
+ *   Dt = den * eta' (d0 n1^2 - (d0.n1) n1) + sgn(d0.n1) sqrt(S) num n1
+ *     (Eq. eq_refr_rational times den = d0 + d1 beta/S; the sign orients n1
+ *     against the incoming ray)
+ *   mapping onto T2 (Eq. eq_rct): q = x1 - p20,
+ *     ut = (Dt x e22).q,  vt = (q x e21).Dt,  kappa = (Dt x e22).e21
+ *   X2 = kappa p20 + ut e21 + vt e22 (= kappa x2),  M2 = kappa n20 + ut dn21 + vt dn22 (= kappa n2),
+ *   D2 = kappa x3 - X2 (= kappa d2).
+ *   Since d1 = x2 - x1 is parallel to Dt, Dt replaces d1 in both constraints at x2:
+ *   a = (Dt x (x3 - x1)) . M2                                         (Eq. eq_coplane)
+ *   b = eta1^2 |D2|^2 ((Dt x M2).b)^2 - eta2^2 |Dt|^2 ((D2 x M2).b)^2  (Eq. eq_cpf_result)
+ *   Structural degrees with D = 3 + 4 f1 (f = 1 for interpolated normals):
+ *   deg a = 2D + 1 + f2, deg b = 6D + 2 + 2 f2, u-degree = total degree.
+ */
+typedef struct { double bp[7]; double c[6][4]; } or_sqrtfit;  /* breakpoints, (c0,c1,d0,d1) per piece */
+
+static int coeffs_tt(arena *A, const tri_t *T1, const tri_t *T2, v3 x0, v3 x3, const double *eta,
+                     const or_sqrtfit *fit, bp *pa, bp *pb, int *flags)
+{
+    int f1 = T1->flat ? 0 : 1, f2 = T2->flat ? 0 : 1;
+    double etap = eta[0] / eta[1];
+    bv x1 = tri_xpoly(A, T1);
+    bv n1 = tri_npoly(A, T1);
+    bv d0 = bv_sub(A, x1, bv_const(A, x0));
+    bp nn = bv_dot(A, n1, n1), dd = bv_dot(A, d0, d0), dn = bv_dot(A, d0, n1);
+    bp nndd = bp_mul(A, nn, dd);
+    bp beta = bp_lc(A, 1.0 - etap * etap, nndd, etap * etap, bp_mul(A, dn, dn));
+    /* per-tuple constants at the centroid of T1 */
+    v3 c1 = tri_x(T1, 1.0 / 3.0, 1.0 / 3.0), nc1 = tri_n(T1, 1.0 / 3.0, 1.0 / 3.0);
+    v3 d0c = vsub(c1, x0);
+    double S = vdot(nc1, nc1) * vdot(d0c, d0c);
+    double dnc = vdot(d0c, nc1);
+    double sc = 1.0 - etap * etap * (1.0 - dnc * dnc / S);   /* beta/S at the centroid */
+    int p = 0;
+    for (int k = 1; k < 6; ++k) if (sc >= fit->bp[k]) p = k;
+    double q0 = fit->c[p][0], q1 = fit->c[p][1], r0 = fit->c[p][2], r1 = fit->c[p][3];
+    bp num = bp_lc(A, q1 / S, beta, q0, bp_const(A, 1.0));
+    bp den = bp_lc(A, r1 / S, beta, r0, bp_const(A, 1.0));
+    double sg = dnc < 0.0 ? -1.0 : 1.0;
+    bv tang = bv_sub(A, bv_smul(A, nn, d0), bv_smul(A, dn, n1));          /* d0 n^2 - (d0.n) n */
+    bv Dt = bv_add(A, bv_kmul(A, etap, bv_smul(A, den, tang)), bv_kmul(A, sg * sqrt(S), bv_smul(A, num, n1)));
+    /* rational coordinate mapping onto T2 */
+    bv q = bv_sub(A, x1, bv_const(A, T2->p0));
+    bv Dxe22 = bv_cross(A, Dt, bv_const(A, T2->e2));
+    bp ut = bv_dot(A, Dxe22, q);
+    bp vt = bv_dot(A, bv_cross(A, q, bv_const(A, T2->e1)), Dt);
+    bp ka = bv_dotc(A, Dxe22, T2->e1);
+    bv X2 = bv_add(A, bv_vmul(A, ka, T2->p0), bv_add(A, bv_vmul(A, ut, T2->e1), bv_vmul(A, vt, T2->e2)));
+    bv M2 = f2 ? bv_add(A, bv_vmul(A, ka, T2->n0), bv_add(A, bv_vmul(A, ut, T2->dn1), bv_vmul(A, vt, T2->dn2)))
+               : bv_vmul(A, ka, T2->n0);
+    bv D2 = bv_sub(A, bv_vmul(A, ka, x3), X2);
+    *pa = bv_dot(A, bv_cross(A, Dt, bv_sub(A, bv_const(A, x3), x1)), M2);
+    v3 c2 = tri_x(T2, 1.0 / 3.0, 1.0 / 3.0);
+    v3 ax;
+    *flags |= pick_axis(c2, c1, x3, &ax);
+    bp l = bv_dotc(A, bv_cross(A, Dt, M2), ax);
+    bp r = bv_dotc(A, bv_cross(A, D2, M2), ax);
+    bp t1 = bp_mul(A, bv_dot(A, D2, D2), bp_mul(A, l, l));
+    bp t2 = bp_mul(A, bv_dot(A, Dt, Dt), bp_mul(A, r, r));
+    *pb = bp_lc(A, eta[1] * eta[1], t1, -eta[2] * eta[2], t2);
+    int D = 3 + 4 * f1;
+    (void)D;
+    return 6 * (3 + 4 * f1) + 2 + 2 * f2;  /* structural u-degree of b = Bezout size */
+}
+
+/* sign of det of the numeric Bezout matrix at v, by Gaussian elimination with
+ * partial pivoting (Sec. 5.2).  Only the sign is formed (the product of the
+ * pivots under- or overflows for large n).  Reading: sgn(0) := +1.          */
+static int det_sign_at(arena *A, bp a, bp b, int n, double v)
+{
+    size_t mark = A->top;
+    double *ai = (double *)ar_alloc(A, sizeof(double) * (size_t)(n + 2));
+    double *bi = (double *)ar_alloc(A, sizeof(double) * (size_t)(n + 2));
+    for (int i = 0; i <= n; ++i) {
+        ai[i] = 0.0; bi[i] = 0.0;
+        if (i <= a.d) for (int j = a.d - i; j >= 0; --j) ai[i] = ai[i] * v + a.c[i * (a.d + 1) + j];
+        if (i <= b.d) for (int j = b.d - i; j >= 0; --j) bi[i] = bi[i] * v + b.c[i * (b.d + 1) + j];
+    }
+    double *M = (double *)ar_alloc(A, sizeof(double) * (size_t)n * (size_t)n);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            double s = 0.0;
+            int kmax = i < n - 1 - j ? i : n - 1 - j;
+            for (int k = 0; k <= kmax; ++k) s += ai[i - k] * bi[j + 1 + k] - bi[i - k] * ai[j + 1 + k];
+            M[i * n + j] = s;
+        }
+    int sign = 1;
+    for (int k = 0; k < n; ++k) {
+        int p = k;
+        double best = fabs(M[k * n + k]);
+        for (int i = k + 1; i < n; ++i) if (fabs(M[i * n + k]) > best) { best = fabs(M[i * n + k]); p = i; }
+        if (!(best > 0.0)) { A->top = mark; return 1; }   /* det == 0 */
+        if (p != k) {
+            for (int j = 0; j < n; ++j) { double t = M[k * n + j]; M[k * n + j] = M[p * n + j]; M[p * n + j] = t; }
+            sign = -sign;
+        }
+        double piv = M[k * n + k];
+        if (piv < 0) sign = -sign;
+        for (int i = k + 1; i < n; ++i) {
+            double l = M[i * n + k] / piv;
+            if (l == 0.0) continue;
+            for (int j = k + 1; j < n; ++j) M[i * n + j] -= l * M[k * n + j];
+        }
+    }
+    A->top = mark;
+    return sign;
+}
+
+/* exact refraction at x1 and intersection with T2's plane.  Returns 0 on total
+ * internal reflection or when the plane is behind / parallel.               */
+static int trace_x2(const tri_t *T1, const tri_t *T2, v3 x0, double u1, double v1, double etap,
+                    double *u2, double *v2, v3 *x1o, v3 *x2o)
+{
+    v3 x1 = tri_x(T1, u1, v1);
+    v3 n = vnorm(tri_n(T1, u1, v1));
+    v3 di = vnorm(vsub(x1, x0));
+    double c = vdot(di, n);
+    if (c > 0) { n = vmul(n, -1.0); c = -c; }          /* orient n against the incoming ray */
+    double ci = -c;
+    double k = 1.0 - etap * etap * (1.0 - ci * ci);
+    if (k < 0.0) return 0;
+    v3 dt = vadd(vmul(di, etap), vmul(n, etap * ci - sqrt(k)));
+    /* Moller-Trumbore without bounds */
+    v3 pv = vcross(dt, T2->e2);
+    double det = vdot(T2->e1, pv);
+    if (!(fabs(det) > 0.0)) return 0;
+    v3 tv = vsub(x1, T2->p0);
+    double uu = vdot(tv, pv) / det;
+    v3 qv = vcross(tv, T2->e1);
+    double vv = vdot(dt, qv) / det;
+    double t = vdot(T2->e2, qv) / det;
+    if (!(t > 0.0)) return 0;
+    *u2 = uu; *v2 = vv; *x1o = x1; *x2o = tri_x(T2, uu, vv);
+    return 1;
+}
+
+/* F(u1,v1): (h2^ x n2^) on a fixed tangent basis of T2, x2 from the exact ray */
+static int tt_residual(const tri_t *T1, const tri_t *T2, v3 x0, v3 x3, const double *eta,
+                       v3 ta, v3 tb, double u1, double v1, double F[2])
+{
+    double u2, v2; v3 x1, x2;
+    if (!trace_x2(T1, T2, x0, u1, v1, eta[0] / eta[1], &u2, &v2, &x1, &x2)) return 0;
+    v3 n2 = vnorm(tri_n(T2, u2, v2));
+    v3 wi = vnorm(vsub(x1, x2)), wo = vnorm(vsub(x3, x2));
+    v3 h = vnorm(vadd(vmul(wi, eta[1]), vmul(wo, eta[2])));
+    v3 g = vcross(h, n2);
+    F[0] = vdot(g, ta); F[1] = vdot(g, tb);
+    return 1;
+}
+
+/* Newton polish with a central-difference Jacobian (reading of the one
+ * Newton iteration of Sec. 7, applied to the exact constraints).            */
+static int polish_tt(const tri_t *T1, const tri_t *T2, v3 x0, v3 x3, const double *eta, int iters,
+                     double *pu, double *pv)
+{
+    v3 nc = vnorm(tri_n(T2, 1.0 / 3.0, 1.0 / 3.0));
+    v3 ref = fabs(nc.x) < 0.9 ? V(1, 0, 0) : V(0, 1, 0);
+    v3 ta = vnorm(vcross(nc, ref)), tb = vcross(nc, ta);
+    double u = *pu, v = *pv, step = 1e300;
+    const double h = 1e-6;
+    for (int it = 0; it < iters; ++it) {
+        double F[2], Fu1[2], Fu0[2], Fv1[2], Fv0[2];
+        if (!tt_residual(T1, T2, x0, x3, eta, ta, tb, u, v, F)) return 0;
+        if (!tt_residual(T1, T2, x0, x3, eta, ta, tb, u + h, v, Fu1)) return 0;
+        if (!tt_residual(T1, T2, x0, x3, eta, ta, tb, u - h, v, Fu0)) return 0;
+        if (!tt_residual(T1, T2, x0, x3, eta, ta, tb, u, v + h, Fv1)) return 0;
+        if (!tt_residual(T1, T2, x0, x3, eta, ta, tb, u, v - h, Fv0)) return 0;
+        double J00 = (Fu1[0] - Fu0[0]) / (2 * h), J10 = (Fu1[1] - Fu0[1]) / (2 * h);
+        double J01 = (Fv1[0] - Fv0[0]) / (2 * h), J11 = (Fv1[1] - Fv0[1]) / (2 * h);
+        double det = J00 * J11 - J01 * J10;
+        if (!(det != 0.0) || !isfinite(det)) return 0;
+        double du = (F[0] * J11 - J01 * F[1]) / det;
+        double dv = (J00 * F[1] - J10 * F[0]) / det;
+        u -= du; v -= dv;
+        step = fabs(du) + fabs(dv);
+        if (!(step > 1e-15)) break;
+    }
+    *pu = u; *pv = v;
+    return step <= 1e-10;
+}
+
+static void solve_tt(arena *A, const tri_t *T1, const tri_t *T2, v3 x0, v3 x3, const double *eta,
+                     const or_sqrtfit *fit, const or_params *prm, int32_t qid,
+                     or_sol *out, int32_t *nout, or_diag *dg)
+{
+    memset(dg, 0, sizeof(*dg));
+    dg->min_gap = 1.0; dg->tangency = 1e300;
+    if (T1->flat) dg->flags |= OR_F_FLAT1;
+    if (T2->flat) dg->flags |= OR_F_FLAT2;
+    bp a, b;
+    int nb = coeffs_tt(A, T1, T2, x0, x3, eta, fit, &a, &b, &dg->flags);
+    int ma = numeric_udeg(a, a.d);
+    nb = numeric_udeg(b, nb);
+    int n = ma > nb ? ma : nb;
+    if (n < 1) { dg->flags |= OR_F_DEGENERATE; *nout = 0; return; }
+    /* piecewise sign scan of det R(v) on [0,1] */
+    int P = prm->pieces;
+    int *sg = (int *)ar_alloc(A, sizeof(int) * (size_t)(P + 1));
+    for (int j = 0; j <= P; ++j) sg[j] = det_sign_at(A, a, b, n, (double)j / P);
+    double vr[OR_MAXSOL * 8];
+    int nv = 0;
+    for (int j = 0; j < P; ++j) {
+        if (sg[j] == sg[j + 1]) continue;
+        double l = (double)j / P, r = (double)(j + 1) / P;
+        int sl = sg[j];
+        for (int it = 0; it < prm->bisect_iters; ++it) {
+            double m = 0.5 * (l + r);
+            if (det_sign_at(A, a, b, n, m) == sl) l = m; else r = m;
+        }
+        if (nv < OR_MAXSOL * 8) vr[nv++] = 0.5 * (l + r);
+    }
+    dg->n_vroots = nv;
+    for (int k = 1; k < nv; ++k) dg->min_gap = fmin(dg->min_gap, vr[k] - vr[k - 1]);
+    int nsol = 0;
+    double etap = eta[0] / eta[1];
+    for (int k = 0; k < nv; ++k) {
+        double v = vr[k];
+        double *auc = (double *)ar_alloc(A, sizeof(double) * (size_t)(ma + 1));
+        for (int i = 0; i <= ma; ++i) {
+            double s = 0.0;
+            for (int j = a.d - i; j >= 0; --j) s = s * v + a.c[i * (a.d + 1) + j];
+            auc[i] = s;
+        }
+        double ur[64];
+        int nu = isolate(A, auc, ma, -prm->u_margin, 1.0 - v + prm->u_margin, ur, 64);
+        for (int m = 0; m < nu; ++m) {
+            double u = ur[m], vv = v;
+            dg->n_cand++;
+            if (!polish_tt(T1, T2, x0, x3, eta, prm->polish_iters, &u, &vv)) continue;
+            if (!bary_inside(u, vv)) continue;
+            double u2, v2; v3 x1, x2;
+            if (!trace_x2(T1, T2, x0, u, vv, etap, &u2, &v2, &x1, &x2)) continue;
+            if (!bary_inside(u2, v2)) continue;
+            double r1, r2;
+            if (!vertex_law(x0, x1, x2, tri_n(T1, u, vv), eta[0], eta[1], 1, &r1)) continue;
+            if (!vertex_law(x1, x2, x3, tri_n(T2, u2, v2), eta[1], eta[2], 1, &r2)) continue;
+            double res = fmax(r1, r2);
+            if (!(res <= prm->tau)) continue;
+            or_sol s;
+            memset(&s, 0, sizeof(s));
+            s.query = qid; s.u1 = u; s.v1 = vv; s.u2 = u2; s.v2 = v2;
+            s.residual = res; s.edge = fmin(edge_dist(u, vv), edge_dist(u2, v2)); s.flags = dg->flags;
+            nsol = add_solution(out, nsol, prm->dedup, s);
+        }
+    }
+    dg->n_valid = nsol;
+    *nout = nsol;
+}
+
+int or_solve_tt(const double *P, const double *N, const int32_t *tri, int64_t nt,
+                const double *x0s, const double *x3s,
+                const int32_t *q_x0, const int32_t *q_x3, const int32_t *q_t1, const int32_t *q_t2, int64_t nq,
+                const double *eta, const or_sqrtfit *fit, const or_params *prm,
+                or_sol *out, int32_t *count, or_diag *diag)
+{
+    (void)nt;
+#pragma omp parallel
+    {
+        arena A;
+        A.cap = (size_t)64 << 20; A.top = 0; A.base = (char *)malloc(A.cap);
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t q = 0; q < nq; ++q) {
+            A.top = 0;
+            tri_t T1 = load_tri(P, N, tri, q_t1[q]);
+            tri_t T2 = load_tri(P, N, tri, q_t2[q]);
+            solve_tt(&A, &T1, &T2, vload(x0s, q_x0[q]), vload(x3s, q_x3[q]), eta, fit, prm, (int32_t)q,
+                     out + q * OR_MAXSOL, count + q, diag + q);
+        }
+        free(A.base);
+    }
+    return 0;
+}
+
+/* TT coefficients for the pin tests (dense (d+1)^2 arrays, capacity 47*47) */
+int or_coeffs_tt(const double *P, const double *N, const int32_t *tri, int64_t t1, int64_t t2,
+                 const double *x0, const double *x3, const double *eta, const or_sqrtfit *fit,
+                 double *a_out, int32_t *da, double *b_out, int32_t *db, int32_t *n_bez, int32_t *flags)
+{
+    arena A; A.cap = (size_t)64 << 20; A.top = 0; A.base = (char *)malloc(A.cap);
+    tri_t T1 = load_tri(P, N, tri, t1), T2 = load_tri(P, N, tri, t2);
+    bp a, b; int fl = 0;
+    int nb = coeffs_tt(&A, &T1, &T2, vload(x0, 0), vload(x3, 0), eta, fit, &a, &b, &fl);
+    int ma = numeric_udeg(a, a.d);
+    nb = numeric_udeg(b, nb);
+    int n = ma > nb ? ma : nb;
+    *da = a.d; *db = b.d; *n_bez = n; *flags = fl;
+    memcpy(a_out, a.c, sizeof(double) * (size_t)(a.d + 1) * (size_t)(a.d + 1));
+    memcpy(b_out, b.c, sizeof(double) * (size_t)(b.d + 1) * (size_t)(b.d + 1));
+    free(A.base);
+    return 0;
+}
+
+/* sign of det R(v) for given bivariate a, b and Bezout size n */
+int or_det_sign(const double *a_in, int32_t da, const double *b_in, int32_t db, int32_t n, double v)
+{
+    arena A; A.cap = (size_t)16 << 20; A.top = 0; A.base = (char *)malloc(A.cap);
+    bp a = bp_new(&A, da), b = bp_new(&A, db);
+    memcpy(a.c, a_in, sizeof(double) * (size_t)(da + 1) * (size_t)(da + 1));
+    memcpy(b.c, b_in, sizeof(double) * (size_t)(db + 1) * (size_t)(db + 1));
+    int s = det_sign_at(&A, a, b, n, v);
+    free(A.base);
+    return s;
+}
+
+int or_maxsol(void) { return OR_MAXSOL; }
