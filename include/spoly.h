@@ -1,0 +1,173 @@
+/*
+ * spoly.h -- C ABI of the MI355X (gfx950) specular-polynomial solver.
+ *
+ * Method: Fan et al., "Specular Polynomials", ACM TOG 43(4), 2024.  For every
+ * candidate (separator x0, separator x_{k+1}, triangle or triangle tuple) the
+ * library finds all admissible specular chains: the vertex constraints
+ * (Sec. 4.2-4.3) and, for two vertices, the rational coordinate mapping
+ * (Sec. 4.4, Eq. eq_rct) give a bivariate system a(u,v) = b(u,v) = 0 in the
+ * barycentrics (u,v) of the first vertex (Sec. 4.5); the hidden-variable Bezout
+ * resultant (Sec. 5.1, Eq. eq_bezout) reduces it to the zeros of det R(v);
+ * those are found by Laplace expansion plus recursive root isolation (one
+ * vertex) or by a piecewise sign scan with bisection (two vertices) (Sec. 5.2);
+ * u follows from a(u)|_v and each candidate is polished in FP64 and kept only
+ * if it lies inside its triangle(s) and satisfies h x n = 0 (Eq. eq_ch)
+ * (Sec. 5.3).
+ *
+ * Conventions (all entry points):
+ *  - Array pointers are DEVICE pointers unless marked [host].  The caller owns
+ *    every buffer; the library allocates device memory only inside a
+ *    spoly_ctx (per-triangle tables, stage buffers), and frees it in
+ *    spoly_ctx_destroy.
+ *  - Work is enqueued asynchronously on `stream` (a hipStream_t, or NULL for
+ *    the null stream).  Results are valid after the stream is synchronised.
+ *  - Argument errors (null pointers, negative sizes, eta <= 0, out-of-range
+ *    enums) are detected on the host before any launch and return
+ *    SPOLY_E_INVALID_ARG; nothing is enqueued then.
+ *  - Capacity: *out_count receives the total number of solutions found, which
+ *    may exceed out_capacity; only the first out_capacity records are written
+ *    (in unspecified order).  A caller that sees *out_count > out_capacity
+ *    re-runs with a larger buffer.  This can only be seen after the stream
+ *    synchronises, so the call itself returns SPOLY_OK.
+ *  - Degenerate instances (zero-length normals, NaN/Inf input, identically
+ *    vanishing resultant) yield no solution and bump counters[2] if
+ *    `counters` is given.
+ *  - Index inputs (vertex ids in the mesh, query ids) must be in range; the
+ *    kernels do not re-check them.
+ *  - Calls on one ctx must not overlap on different streams.
+ */
+#ifndef SPOLY_H
+#define SPOLY_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SPOLY_OK = 0,
+    SPOLY_E_INVALID_ARG = 1,
+    SPOLY_E_CAPACITY = 2,
+    SPOLY_E_DEVICE = 3,
+    SPOLY_E_UNSUPPORTED = 4
+} spoly_status;
+
+/* scattering event at a specular vertex (Sec. 4.5: R = reflection, T = refraction) */
+typedef enum { SPOLY_R = 0, SPOLY_T = 1 } spoly_event;
+
+/* arithmetic of the bulk stages; the final polish and validation are always FP64 */
+typedef enum {
+    SPOLY_FP64 = 0,          /* every stage in double precision                           */
+    SPOLY_FP32_POLISH64 = 1  /* coefficients, elimination and root isolation in float;   */
+                             /* root polish, path phase and validation in double          */
+} spoly_precision;
+
+/* Triangle mesh, structure of arrays.  px..pz: vertex positions, nx..nz: vertex
+ * normals (need not be unit length; the interpolated normal N u of Eq. eq_ni
+ * is used un-normalised), all double [n_vertices].  tri: int32 [3*n_tris],
+ * the vertex ids of triangle t are tri[3t], tri[3t+1], tri[3t+2]; e1 = p1 - p0,
+ * e2 = p2 - p0 (Table 1). */
+typedef struct {
+    const double *px, *py, *pz;
+    const double *nx, *ny, *nz;
+    const int32_t *tri;
+    int32_t n_vertices, n_tris;
+} spoly_mesh;
+
+/* separator points (shading points, receivers, lights): double [n] each */
+typedef struct {
+    const double *x, *y, *z;
+    int32_t n;
+} spoly_points;
+
+/* Solver parameters [host].  spoly_default_params() fills the values used
+ * throughout (pieces = 100 and bisect_iters = 10 from Sec. 5.2, iso_eps = 1e-9
+ * from Sec. 5.2, tau = 1e-6 on |h^ x n^|). */
+typedef struct {
+    int32_t pieces;        /* uniform pieces of [0,1] for the >= 2-vertex sign scan      */
+    int32_t bisect_iters;  /* bisection steps per sign change                            */
+    double iso_eps;        /* one-vertex isolation stops below this interval length      */
+    double tau;            /* path-space tolerance on |h^ x n^| at every vertex          */
+    double u_margin;       /* u is searched on [-m, 1-v+m] before the polish             */
+    double dedup;          /* candidates closer than this in (u,v) are one solution      */
+    int32_t polish_iters;  /* maximum FP64 Newton steps of the polish                    */
+    uint32_t flags;        /* reserved, 0                                                */
+} spoly_params;
+
+/* One admissible chain.  For one vertex tri[1] = -1 and u[1] = v[1] = 0. */
+typedef struct {
+    int32_t query;         /* index into the query arrays                                */
+    int32_t tri[2];        /* triangle ids of x1 (and x2)                                */
+    uint32_t flags;        /* reserved                                                   */
+    double u[2], v[2];     /* barycentrics of x1 (and x2), Eq. eq_xi                     */
+    float residual;        /* max over the chain of |h^ x n^| after polish               */
+    float edge;            /* min over the chain of min(u, v, 1-u-v)                     */
+} spoly_solution;
+
+typedef struct spoly_ctx spoly_ctx;
+
+/* Create a context on HIP device `device` (also made current).  *ctx receives
+ * the handle.  SPOLY_E_DEVICE if the device cannot be used. */
+spoly_status spoly_ctx_create(spoly_ctx **ctx, int device);
+/* Free the context and all device memory it owns.  NULL is ignored. */
+void spoly_ctx_destroy(spoly_ctx *ctx);
+
+/* Fill *p [host] with the default parameters. */
+void spoly_default_params(spoly_params *p);
+
+/* Human-readable name of a status code (static storage). */
+const char *spoly_status_str(spoly_status s);
+
+/*
+ * S0 -- conservative normal-cone cull for one specular vertex.
+ * For every (x0 in x0s, x2 in x2s, triangle) triple, keep it unless no
+ * generalised half vector h = eta0 w0 + eta1 w2 (w0, w2 unit directions from a
+ * point of the triangle to x0 and x2) can be parallel to an interpolated normal
+ * N u: with direction cones from the triangle's bounding sphere to x0 and x2
+ * and the cone of the three vertex normals, the triple is rejected iff the
+ * angle between the normal-cone axis line and the centre half vector exceeds
+ * the normal-cone half angle plus the half-vector spread plus `margin`
+ * radians.  Evaluated in float with the outward margin, so every triple with
+ * an admissible chain is kept (h x n = 0 of Eq. eq_ch holds only if h is
+ * parallel to the normal).
+ * Output: kept triples as three int32 arrays out_x0, out_x2, out_tri
+ * [out_capacity]; *out_count (device, uint64) receives the total kept, which
+ * may exceed the capacity (the excess is not written).  *out_count must be
+ * zeroed by the caller before the call (the kernel accumulates into it).
+ * Order of the output is unspecified.
+ */
+spoly_status spoly_cull_1bounce(spoly_ctx *ctx, const spoly_mesh *mesh,
+                                const spoly_points *x0s, const spoly_points *x2s,
+                                double eta0, double eta1, double margin,
+                                int32_t *out_x0, int32_t *out_x2, int32_t *out_tri,
+                                int64_t out_capacity, unsigned long long *out_count, void *stream);
+
+/*
+ * S1-S7 for one specular vertex (Sec. 4.5 systems R and T).
+ * Query q solves the chain x0s[q_x0[q]] -> triangle q_tri[q] -> x2s[q_x2[q]].
+ * eta0: IOR of the medium of x0, eta1: IOR of the medium of x2 (Eq. eq_ch;
+ * reflection uses eta0 = eta1).  R requires both endpoints on the same side of
+ * the normal, T opposite sides.
+ * out [out_capacity] receives solution records; *out_count (device uint64,
+ * zeroed by the caller) the total number found.
+ * counters (optional, device uint64 [4], accumulated): [0] real roots of r(v)
+ * found in [0,1], [1] (u,v) candidates polished, [2] degenerate instances,
+ * [3] reserved.
+ * diag_q (optional, device int32 [2*n_queries]): per query the number of roots
+ * of r(v) in [0,1] and the number of solutions.
+ */
+spoly_status spoly_solve_1bounce(spoly_ctx *ctx, const spoly_mesh *mesh,
+                                 const spoly_points *x0s, const spoly_points *x2s,
+                                 const int32_t *q_x0, const int32_t *q_x2, const int32_t *q_tri,
+                                 int64_t n_queries, spoly_event ev, double eta0, double eta1,
+                                 spoly_precision prec, const spoly_params *params,
+                                 spoly_solution *out, int64_t out_capacity,
+                                 unsigned long long *out_count, unsigned long long *counters,
+                                 int32_t *diag_q, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPOLY_H */

@@ -70,6 +70,8 @@ def lib():
         L.or_isolate.argtypes = [P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, P, ctypes.c_int32]
         L.or_det_sign.argtypes = [P, ctypes.c_int32, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double]
         L.or_maxsol.restype = ctypes.c_int
+        L.or_cull_1bounce.argtypes = [P, P, P, ctypes.c_int64, P, ctypes.c_int64, P, ctypes.c_int64,
+                                      ctypes.c_double, ctypes.c_double, ctypes.c_double, P]
         _lib = L
     return _lib
 
@@ -209,3 +211,14 @@ def det_sign(A: np.ndarray, B: np.ndarray, n: int, v: float) -> int:
     A = _c(A, np.float64)
     B = _c(B, np.float64)
     return int(L.or_det_sign(_p(A), A.shape[0] - 1, _p(B), B.shape[0] - 1, n, v))
+
+
+def cull_1bounce(P, N, tri, x0s, x2s, eta0=1.0, eta1=1.0, margin=0.0) -> np.ndarray:
+    """Keep mask [n0, n2, nt] (bool) of the FP64 normal-cone cull."""
+    L = lib()
+    P, N, x0s, x2s = (_c(a, np.float64) for a in (P, N, x0s, x2s))
+    tri = _c(tri, np.int32)
+    n0, n2, nt = len(x0s), len(x2s), len(tri)
+    keep = np.zeros(n0 * n2 * nt, dtype=np.uint8)
+    L.or_cull_1bounce(_p(P), _p(N), _p(tri), nt, _p(x0s), n0, _p(x2s), n2, eta0, eta1, margin, _p(keep))
+    return keep.reshape(n0, n2, nt).astype(bool)

@@ -32,6 +32,7 @@
  * beyond what those steps say.  Readings of points the paper leaves open are
  * listed in the design notes and repeated at the place they apply.
  */
+#define _GNU_SOURCE
 #include <math.h>
 #include <stdint.h>
 #include <stdio.h>
@@ -969,3 +970,52 @@ int or_det_sign(const double *a_in, int32_t da, const double *b_in, int32_t db, 
 }
 
 int or_maxsol(void) { return OR_MAXSOL; }
+
+/* ================================================================== S0 twin: normal-cone cull (FP64)
+ * keep[(j0*n2 + j2)*nt + t] = 1 unless the cone of generalised half vectors
+ * h = eta0 w0 + eta1 w2 (w0, w2: unit directions from a point of the
+ * triangle's bounding sphere to x0 and x2) cannot meet the cone of the vertex
+ * normals: with chord bounds |w - a| <= 2 sin(theta/2), h lies within
+ * asin(delta/L) of H = eta0 a0 + eta1 a2 (L = |H|, delta = eta0 ch0 + eta1 ch2);
+ * h x n = 0 needs the angle between the lines of H and of the normal-cone axis
+ * to be at most theta_n + asin(delta/L).  `margin` (radians) widens the test.  */
+int or_cull_1bounce(const double *P, const double *N, const int32_t *tri, int64_t nt,
+                    const double *x0s, int64_t n0, const double *x2s, int64_t n2,
+                    double eta0, double eta1, double margin, uint8_t *keep)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t t = 0; t < nt; ++t) {
+        v3 p[3], n[3];
+        for (int k = 0; k < 3; ++k) { p[k] = vload(P, tri[3 * t + k]); n[k] = vnorm(vload(N, tri[3 * t + k])); }
+        v3 c = vmul(vadd(vadd(p[0], p[1]), p[2]), 1.0 / 3.0);
+        double rad = fmax(fmax(vlen(vsub(p[0], c)), vlen(vsub(p[1], c))), vlen(vsub(p[2], c)));
+        v3 an = vadd(vadd(n[0], n[1]), n[2]);
+        double lan = vlen(an);
+        an = vnorm(an);
+        double thn = 0.0;
+        for (int k = 0; k < 3; ++k) thn = fmax(thn, acos(fmin(1.0, fmax(-1.0, vdot(an, n[k])))));
+        for (int64_t j0 = 0; j0 < n0; ++j0)
+            for (int64_t j2 = 0; j2 < n2; ++j2) {
+                int k = 1;
+                v3 va = vsub(vload(x0s, j0), c), vb = vsub(vload(x2s, j2), c);
+                double da = vlen(va), db = vlen(vb);
+                if (lan > 0.5 && thn < M_PI / 2 && da > rad && db > rad) {
+                    v3 aa = vmul(va, 1.0 / da), ab = vmul(vb, 1.0 / db);
+                    double sa = rad / da, sb = rad / db;
+                    double cha = sqrt(fmax(0.0, 2.0 - 2.0 * sqrt(fmax(0.0, 1.0 - sa * sa))));
+                    double chb = sqrt(fmax(0.0, 2.0 - 2.0 * sqrt(fmax(0.0, 1.0 - sb * sb))));
+                    v3 H = vadd(vmul(aa, eta0), vmul(ab, eta1));
+                    double L = vlen(H), delta = eta0 * cha + eta1 * chb;
+                    if (delta < L) {
+                        double lim = thn + asin(delta / L) + margin;
+                        if (lim < M_PI / 2) {
+                            double cphi = fabs(vdot(an, H)) / L;
+                            k = cphi >= cos(lim);
+                        }
+                    }
+                }
+                keep[(j0 * n2 + j2) * nt + t] = (uint8_t)k;
+            }
+    }
+    return 0;
+}

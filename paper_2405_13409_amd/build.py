@@ -1,0 +1,54 @@
+"""Build libspoly.so (gfx950) in-tree with hipcc.
+
+The elimination phase of the one-vertex kernels is generated code
+(csrc/gen_laplace.py -> csrc/laplace_gen.inc); it is regenerated on every build.
+"""
+from __future__ import annotations
+
+import glob
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libspoly.so")
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+HIP_FLAGS = [
+    "--offload-arch=gfx950",
+    "-O3",
+    "-std=c++17",
+    "-fPIC",
+    "-shared",
+    # packed FP32 instructions are kept out of every kernel
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+]
+
+
+def generate() -> None:
+    out = subprocess.check_output([sys.executable, os.path.join(CSRC, "gen_laplace.py")])
+    path = os.path.join(CSRC, "laplace_gen.inc")
+    old = open(path, "rb").read() if os.path.exists(path) else b""
+    if old != out:
+        with open(path, "wb") as f:
+            f.write(out)
+
+
+def sources():
+    return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+
+
+def build(verbose: bool = False) -> str:
+    generate()
+    tmp = LIB + ".tmp"
+    cmd = [HIPCC, *HIP_FLAGS, "-o", tmp, *sources()]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

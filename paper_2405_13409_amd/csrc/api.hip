@@ -1,0 +1,143 @@
+// Host side of the C ABI declared in include/spoly.h: argument checks, the
+// context (device buffers it owns) and kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <cstdlib>
+#include <cstring>
+
+#include "../../include/spoly.h"
+#include "onebounce.hpp"
+
+struct spoly_ctx {
+    int device;
+    float4* tri_cone;      // 2 float4 per triangle, grown on demand
+    int64_t tri_cone_cap;  // in triangles
+};
+
+namespace {
+
+bool mesh_ok(const spoly_mesh* m)
+{
+    return m && m->px && m->py && m->pz && m->nx && m->ny && m->nz && m->tri && m->n_vertices > 0 && m->n_tris > 0;
+}
+bool pts_ok(const spoly_points* p) { return p && p->x && p->y && p->z && p->n > 0; }
+
+spoly_status dev_err(hipError_t e) { return e == hipSuccess ? SPOLY_OK : SPOLY_E_DEVICE; }
+
+}  // namespace
+
+extern "C" {
+
+void spoly_default_params(spoly_params* p)
+{
+    if (!p) return;
+    p->pieces = 100;
+    p->bisect_iters = 10;
+    p->iso_eps = 1e-9;
+    p->tau = 1e-6;
+    p->u_margin = 1e-4;
+    p->dedup = 1e-8;
+    p->polish_iters = 6;
+    p->flags = 0;
+}
+
+const char* spoly_status_str(spoly_status s)
+{
+    switch (s) {
+    case SPOLY_OK: return "ok";
+    case SPOLY_E_INVALID_ARG: return "invalid argument";
+    case SPOLY_E_CAPACITY: return "output capacity exceeded";
+    case SPOLY_E_DEVICE: return "device error";
+    case SPOLY_E_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+spoly_status spoly_ctx_create(spoly_ctx** ctx, int device)
+{
+    if (!ctx) return SPOLY_E_INVALID_ARG;
+    *ctx = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return SPOLY_E_DEVICE;
+    if (hipSetDevice(device) != hipSuccess) return SPOLY_E_DEVICE;
+    spoly_ctx* c = static_cast<spoly_ctx*>(std::calloc(1, sizeof(spoly_ctx)));
+    if (!c) return SPOLY_E_DEVICE;
+    c->device = device;
+    *ctx = c;
+    return SPOLY_OK;
+}
+
+void spoly_ctx_destroy(spoly_ctx* ctx)
+{
+    if (!ctx) return;
+    if (ctx->tri_cone) (void)hipFree(ctx->tri_cone);
+    std::free(ctx);
+}
+
+spoly_status spoly_cull_1bounce(spoly_ctx* ctx, const spoly_mesh* mesh, const spoly_points* x0s,
+                                const spoly_points* x2s, double eta0, double eta1, double margin, int32_t* out_x0,
+                                int32_t* out_x2, int32_t* out_tri, int64_t out_capacity,
+                                unsigned long long* out_count, void* stream)
+{
+    if (!ctx || !mesh_ok(mesh) || !pts_ok(x0s) || !pts_ok(x2s) || !out_count || out_capacity < 0) return SPOLY_E_INVALID_ARG;
+    if (out_capacity > 0 && (!out_x0 || !out_x2 || !out_tri)) return SPOLY_E_INVALID_ARG;
+    if (!(eta0 > 0.0) || !(eta1 > 0.0) || !(margin >= 0.0)) return SPOLY_E_INVALID_ARG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (hipSetDevice(ctx->device) != hipSuccess) return SPOLY_E_DEVICE;
+    if (ctx->tri_cone_cap < mesh->n_tris) {
+        if (ctx->tri_cone) (void)hipFree(ctx->tri_cone);
+        ctx->tri_cone = nullptr;
+        ctx->tri_cone_cap = 0;
+        if (hipMalloc(&ctx->tri_cone, sizeof(float4) * 2 * size_t(mesh->n_tris)) != hipSuccess) return SPOLY_E_DEVICE;
+        ctx->tri_cone_cap = mesh->n_tris;
+    }
+    hipError_t e = spoly::launch_tri_cones(mesh->px, mesh->py, mesh->pz, mesh->nx, mesh->ny, mesh->nz, mesh->tri,
+                                           mesh->n_tris, ctx->tri_cone, s);
+    if (e != hipSuccess) return SPOLY_E_DEVICE;
+    spoly::CullArgs A;
+    A.tri_cone = ctx->tri_cone;
+    A.n_tris = mesh->n_tris;
+    A.x0x = x0s->x; A.x0y = x0s->y; A.x0z = x0s->z;
+    A.x2x = x2s->x; A.x2y = x2s->y; A.x2z = x2s->z;
+    A.n0 = x0s->n; A.n2 = x2s->n;
+    A.eta0 = float(eta0); A.eta1 = float(eta1); A.margin = float(margin);
+    A.out_x0 = out_x0; A.out_x2 = out_x2; A.out_tri = out_tri;
+    A.cap = out_capacity;
+    A.out_count = out_count;
+    return dev_err(spoly::launch_cull_1bounce(A, s));
+}
+
+spoly_status spoly_solve_1bounce(spoly_ctx* ctx, const spoly_mesh* mesh, const spoly_points* x0s,
+                                 const spoly_points* x2s, const int32_t* q_x0, const int32_t* q_x2,
+                                 const int32_t* q_tri, int64_t n_queries, spoly_event ev, double eta0, double eta1,
+                                 spoly_precision prec, const spoly_params* params, spoly_solution* out,
+                                 int64_t out_capacity, unsigned long long* out_count, unsigned long long* counters,
+                                 int32_t* diag_q, void* stream)
+{
+    if (!ctx || !mesh_ok(mesh) || !pts_ok(x0s) || !pts_ok(x2s) || !params || !out_count) return SPOLY_E_INVALID_ARG;
+    if (n_queries < 0 || out_capacity < 0 || (out_capacity > 0 && !out)) return SPOLY_E_INVALID_ARG;
+    if (n_queries > 0 && (!q_x0 || !q_x2 || !q_tri)) return SPOLY_E_INVALID_ARG;
+    if (ev != SPOLY_R && ev != SPOLY_T) return SPOLY_E_INVALID_ARG;
+    if (prec != SPOLY_FP64 && prec != SPOLY_FP32_POLISH64) return SPOLY_E_INVALID_ARG;
+    if (!(eta0 > 0.0) || !(eta1 > 0.0)) return SPOLY_E_INVALID_ARG;
+    if (!(params->tau > 0.0) || !(params->iso_eps > 0.0) || params->polish_iters < 0 || !(params->u_margin >= 0.0) ||
+        !(params->dedup >= 0.0))
+        return SPOLY_E_INVALID_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess) return SPOLY_E_DEVICE;
+    spoly::OneBounceArgs A;
+    A.px = mesh->px; A.py = mesh->py; A.pz = mesh->pz;
+    A.nx = mesh->nx; A.ny = mesh->ny; A.nz = mesh->nz;
+    A.tri = mesh->tri;
+    A.x0x = x0s->x; A.x0y = x0s->y; A.x0z = x0s->z;
+    A.x2x = x2s->x; A.x2y = x2s->y; A.x2z = x2s->z;
+    A.q_x0 = q_x0; A.q_x2 = q_x2; A.q_tri = q_tri;
+    A.nq = n_queries;
+    A.eta0 = eta0; A.eta1 = eta1;
+    A.iso_eps = params->iso_eps; A.tau = params->tau; A.u_margin = params->u_margin; A.dedup = params->dedup;
+    A.polish_iters = params->polish_iters;
+    A.out = out; A.cap = out_capacity; A.out_count = out_count;
+    A.counters = counters; A.diag_q = diag_q;
+    return dev_err(spoly::launch_onebounce(A, int(ev), int(prec), static_cast<hipStream_t>(stream)));
+}
+
+}  // extern "C"

@@ -1,0 +1,482 @@
+// One specular vertex (systems R and T of Sec. 4.5): coefficient phase,
+// Bezout elimination with Laplace expansion, recursive root isolation in v,
+// u from a(u)|_v, FP64 Newton polish, path-space validation and wave-ballot
+// compaction -- one instance per lane, everything in registers.
+#include "spoly_dev.hpp"
+#include "laplace_gen.inc"
+#include "onebounce.hpp"
+
+namespace spoly {
+
+constexpr int kMaxLaneSol = 4;
+
+struct Geo {            // FP64 geometry of one instance (after the edge relabelling)
+    V3<double> p0, e1, e2, n0, dn1, dn2, x0, x2;
+    int axis;           // square-form projection axis (T)
+    bool flat;          // all three vertex normals equal
+    bool swapped;       // vertices 1 and 2 exchanged: (u, v) of the kernel = (v, u) of the mesh
+};
+
+// ---------------------------------------------------------------- rules (FP64, as the oracle)
+// Product form tangent t = n x e1 unless e1 nearly lies in the incidence plane
+// (|e1^.m_c| < 1/4 and e2 does better), then t = n x e2.  Instead of using the
+// u-degree-4 system of t = n x e2, the kernel exchanges the triangle's
+// vertices 1 and 2: the system is then of the t = n x e1 shape in (u', v') =
+// (v, u), whose Bezout size is 3 in u'.
+__device__ __forceinline__ bool pick_edge2(V3<double> c, V3<double> xa, V3<double> xb, V3<double> e1, V3<double> e2)
+{
+    V3<double> m = cross(c - xa, xb - xa);
+    double l = len(m);
+    if (!(l > 0.0)) return false;
+    m = m * (1.0 / l);
+    double g1 = fabs(dot(normalized(e1), m)), g2 = fabs(dot(normalized(e2), m));
+    return g1 < 0.25 && g2 > g1;
+}
+// Square form axis: x^ if |m_c.x^| >= 1/2, else z^ if |m_c.z^| >= 1/2, else y^.
+__device__ __forceinline__ int pick_axis(V3<double> c, V3<double> xa, V3<double> xb)
+{
+    V3<double> m = cross(c - xa, xb - xa);
+    double l = len(m);
+    if (!(l > 0.0)) return 0;
+    m = m * (1.0 / l);
+    if (fabs(m.x) >= 0.5) return 0;
+    if (fabs(m.z) >= 0.5) return 2;
+    return 1;
+}
+
+// ---------------------------------------------------------------- coefficient phase
+// a = ((x1 - x0) x (x2 - x0)) . n                          (Eq. eq_coplane)
+// R: b = (d0.n)(d1.t) + (d0.t)(d1.n), t = n x e1           (Eq. eq_pf_result)
+// T: b = eta0^2 |d1|^2 ((d0 x n).ax)^2 - eta1^2 |d0|^2 ((d1 x n).ax)^2   (Eq. eq_cpf_result)
+template <typename R, int EV, int F>
+struct Sys {
+    static constexpr int TA = 1 + F;
+    static constexpr int TB = EV == SPOLY_R ? 2 + 2 * F : 4 + 2 * F;
+    static constexpr int N = EV == SPOLY_R ? 1 + 2 * F : 4 + 2 * F;
+    static constexpr int DR = N * (TA + TB - 1) - N * (N - 1);
+};
+
+template <typename R, int F>
+struct NormalPoly;
+template <typename R>
+struct NormalPoly<R, 0> {
+    static __device__ __forceinline__ VP<R, 0> make(const Geo& g) { return vp_const(cvt<R>(g.n0)); }
+};
+template <typename R>
+struct NormalPoly<R, 1> {
+    static __device__ __forceinline__ VP<R, 1> make(const Geo& g)
+    {
+        return vp_affine(cvt<R>(g.n0), cvt<R>(g.dn1), cvt<R>(g.dn2));
+    }
+};
+
+template <typename R, int EV, int F>
+__device__ __forceinline__ void build_ab(const Geo& g, double eta0, double eta1, P2<R, 1 + F>& a,
+                                         P2<R, Sys<R, EV, F>::TB>& b)
+{
+    VP<R, 1> x1 = vp_affine(cvt<R>(g.p0), cvt<R>(g.e1), cvt<R>(g.e2));
+    auto n = NormalPoly<R, F>::make(g);
+    VP<R, 1> d0 = x1 - vp_const(cvt<R>(g.x0));
+    VP<R, 1> d1 = vp_const(cvt<R>(g.x2)) - x1;
+    VP<R, 0> w = vp_const(cvt<R>(g.x2 - g.x0));
+    a = vdot(vcross(d0, w), n);
+    if constexpr (EV == SPOLY_R) {
+        auto t = vcross(n, vp_const(cvt<R>(g.e1)));
+        auto full = vdot(d0, n) * vdot(d1, t) + vdot(d0, t) * vdot(d1, n);
+        b = full;
+    } else {
+        auto l = vcomp(vcross(d0, n), g.axis);
+        auto r = vcomp(vcross(d1, n), g.axis);
+        auto t1 = vdot(d1, d1) * (l * l);
+        auto t2 = vdot(d0, d0) * (r * r);
+        b = lc(R(eta0 * eta0), t1, R(-eta1 * eta1), t2);
+    }
+}
+
+template <typename R, int D>
+__device__ __forceinline__ R normalise(P2<R, D>& p)
+{
+    R m = R(0);
+#pragma unroll
+    for (int k = 0; k < tri_size(D); ++k) m = fmax(m, fabs(p.c[k]));
+    if (m > R(0)) {
+        R s = R(1) / m;
+#pragma unroll
+        for (int k = 0; k < tri_size(D); ++k) p.c[k] *= s;
+    }
+    return m;
+}
+
+template <typename R, int EV, int F>
+__device__ __forceinline__ void eliminate(const R* A, const R* B, R* r)
+{
+    if constexpr (EV == SPOLY_R && F == 1) elim_r_interp<R>(A, B, r);
+    else if constexpr (EV == SPOLY_R && F == 0) elim_r_flat<R>(A, B, r);
+    else if constexpr (EV == SPOLY_T && F == 1) elim_t_interp<R>(A, B, r);
+    else elim_t_flat<R>(A, B, r);
+}
+
+// ---------------------------------------------------------------- univariate solve (Sec. 5.2)
+// Recursive isolation on [0,1]: the roots of p' split [0,1] into monotone
+// pieces; a piece with a strict sign change (sgn(0) := +1) holds one root,
+// bisected until the interval is shorter than eps.  Roots are kept in the slot
+// of the piece they come from (no compaction, so every register index is a
+// compile-time constant); ok[k] marks a root in slot k.
+template <typename R, int D>
+__device__ __forceinline__ R bisect(const R (&c)[D + 1], R lo, R hi, bool neg_lo, R eps)
+{
+    for (int it = 0; it < 80; ++it) {
+        if (!(hi - lo > eps)) break;
+        R m = (lo + hi) * R(0.5);
+        if (!(m > lo && m < hi)) break;
+        bool neg = horner<R, D>(c, m) < R(0);
+        if (neg == neg_lo) lo = m;
+        else hi = m;
+    }
+    return (lo + hi) * R(0.5);
+}
+
+template <typename R, int D>
+__device__ __forceinline__ void scan_pieces(const R (&c)[D + 1], const R (&bp)[D], const bool (&bok)[D],
+                                            R (&rt)[D + 1], bool (&ok)[D + 1], R eps)
+{
+    R lo = R(0), flo = horner<R, D>(c, R(0));
+    R last = R(-1e30);
+#pragma unroll
+    for (int k = 0; k <= D; ++k) {
+        ok[k] = false;
+        rt[k] = R(0);
+        bool has = (k < D) ? bok[k] : true;
+        R hi = (k < D) ? bp[k] : R(1);
+        if (has) {
+            R fhi = horner<R, D>(c, hi);
+            if (hi > lo && ((flo < R(0)) != (fhi < R(0)))) {
+                R x = bisect<R, D>(c, lo, hi, flo < R(0), eps);
+                if (x - last > R(1e-12)) {
+                    rt[k] = x;
+                    ok[k] = true;
+                    last = x;
+                }
+            }
+            lo = hi;
+            flo = fhi;
+        }
+    }
+}
+
+template <typename R, int D>
+__device__ __forceinline__ void isolate01(const R (&c)[D + 1], R (&rt)[D + 1], bool (&ok)[D + 1], R eps)
+{
+    R bp[D];
+    bool bok[D];
+    if constexpr (D == 1) {
+        bok[0] = false;
+        bp[0] = R(0);
+    } else {
+        R dc[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) dc[k] = c[k + 1] * R(k + 1);
+        R brt[D];
+        bool bbok[D];
+        isolate01<R, D - 1>(dc, brt, bbok, eps);
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            bp[k] = brt[k];
+            bok[k] = bbok[k];
+        }
+    }
+    scan_pieces<R, D>(c, bp, bok, rt, ok, eps);
+}
+
+// ---------------------------------------------------------------- path phase (FP64)
+// a, b and their partial derivatives evaluated directly from the geometry.
+template <int EV>
+__device__ __forceinline__ void eval_ab(const Geo& g, double eta0, double eta1, double u, double v, double& fa,
+                                        double& au, double& av, double& fb, double& bu, double& bv)
+{
+    V3<double> x1 = g.p0 + g.e1 * u + g.e2 * v;
+    V3<double> n = g.n0 + g.dn1 * u + g.dn2 * v;
+    V3<double> d0 = x1 - g.x0, d1 = g.x2 - x1, w = g.x2 - g.x0;
+    V3<double> cw = cross(d0, w);
+    fa = dot(cw, n);
+    au = dot(cross(g.e1, w), n) + dot(cw, g.dn1);
+    av = dot(cross(g.e2, w), n) + dot(cw, g.dn2);
+    if constexpr (EV == SPOLY_R) {
+        V3<double> t = cross(n, g.e1), tu = cross(g.dn1, g.e1), tv = cross(g.dn2, g.e1);
+        double p = dot(d0, n), q = dot(d1, t), r = dot(d0, t), s = dot(d1, n);
+        double pu = dot(g.e1, n) + dot(d0, g.dn1), pv = dot(g.e2, n) + dot(d0, g.dn2);
+        double qu = -dot(g.e1, t) + dot(d1, tu), qv = -dot(g.e2, t) + dot(d1, tv);
+        double ru = dot(g.e1, t) + dot(d0, tu), rv = dot(g.e2, t) + dot(d0, tv);
+        double su = -dot(g.e1, n) + dot(d1, g.dn1), sv = -dot(g.e2, n) + dot(d1, g.dn2);
+        fb = p * q + r * s;
+        bu = pu * q + p * qu + ru * s + r * su;
+        bv = pv * q + p * qv + rv * s + r * sv;
+    } else {
+        auto comp = [&](V3<double> x) { return g.axis == 0 ? x.x : (g.axis == 1 ? x.y : x.z); };
+        double l = comp(cross(d0, n)), r = comp(cross(d1, n));
+        double lu = comp(cross(g.e1, n) + cross(d0, g.dn1)), lv = comp(cross(g.e2, n) + cross(d0, g.dn2));
+        double ru = comp(cross(g.e1 * -1.0, n) + cross(d1, g.dn1)), rv = comp(cross(g.e2 * -1.0, n) + cross(d1, g.dn2));
+        double s1 = dot(d1, d1), s0 = dot(d0, d0);
+        double s1u = -2.0 * dot(d1, g.e1), s1v = -2.0 * dot(d1, g.e2);
+        double s0u = 2.0 * dot(d0, g.e1), s0v = 2.0 * dot(d0, g.e2);
+        double k0 = eta0 * eta0, k1 = eta1 * eta1;
+        fb = k0 * s1 * l * l - k1 * s0 * r * r;
+        bu = k0 * (s1u * l * l + 2.0 * s1 * l * lu) - k1 * (s0u * r * r + 2.0 * s0 * r * ru);
+        bv = k0 * (s1v * l * l + 2.0 * s1 * l * lv) - k1 * (s0v * r * r + 2.0 * s0 * r * rv);
+    }
+}
+
+template <int EV>
+__device__ __forceinline__ bool polish(const Geo& g, double eta0, double eta1, int iters, double& u, double& v)
+{
+    double step = 1e300;
+    for (int it = 0; it < iters; ++it) {
+        double fa, au, av, fb, bu, bv;
+        eval_ab<EV>(g, eta0, eta1, u, v, fa, au, av, fb, bu, bv);
+        double det = au * bv - av * bu;
+        if (!(det != 0.0) || !isfinite(det)) break;
+        double du = (fa * bv - av * fb) / det;
+        double dv = (au * fb - fa * bu) / det;
+        u -= du;
+        v -= dv;
+        step = fabs(du) + fabs(dv);
+        if (!(step > 1e-16)) break;
+    }
+    return step <= 1e-10;
+}
+
+// Path-space check of Eq. eq_ch: wi, wo unit directions to the neighbours,
+// h = eta_in wi + eta_out wo; admissible iff |h^ x n^| <= tau and the sides
+// agree with the event ((wi.n)(wo.n) > 0 for R, < 0 for T).
+__device__ __forceinline__ bool vertex_law(V3<double> xp, V3<double> x, V3<double> xn, V3<double> nrm, double ein,
+                                           double eout, bool refract, double& res)
+{
+    double ln = len(nrm);
+    if (!(ln > 1e-12)) {
+        res = 1e300;
+        return false;
+    }
+    V3<double> nh = nrm * (1.0 / ln);
+    V3<double> wi = normalized(xp - x), wo = normalized(xn - x);
+    V3<double> h = wi * ein + wo * eout;
+    double lh = len(h);
+    if (!(lh > 0.0)) {
+        res = 1e300;
+        return false;
+    }
+    res = len(cross(h * (1.0 / lh), nh));
+    double side = dot(wi, nh) * dot(wo, nh);
+    return refract ? side < 0.0 : side > 0.0;
+}
+
+struct LaneSols {
+    double u[kMaxLaneSol], v[kMaxLaneSol], res[kMaxLaneSol], edge[kMaxLaneSol];
+    int n;
+};
+
+__device__ __forceinline__ void push_sol(LaneSols& S, double u, double v, double res, double edge, double dedup)
+{
+    bool dup = false;
+#pragma unroll
+    for (int k = 0; k < kMaxLaneSol; ++k)
+        if (k < S.n && fabs(S.u[k] - u) < dedup && fabs(S.v[k] - v) < dedup) dup = true;
+    if (dup) return;
+#pragma unroll
+    for (int k = 0; k < kMaxLaneSol; ++k)
+        if (k == S.n) {
+            S.u[k] = u;
+            S.v[k] = v;
+            S.res[k] = res;
+            S.edge[k] = edge;
+        }
+    if (S.n < kMaxLaneSol) S.n++;
+}
+
+template <typename R, int EV, int F>
+__device__ __forceinline__ void solve_instance(const Geo& g, const OneBounceArgs& A, LaneSols& S, int& nvr,
+                                               int& ncand, int& degen)
+{
+    using Y = Sys<R, EV, F>;
+    P2<R, Y::TA> a;
+    P2<R, Y::TB> b;
+    build_ab<R, EV, F>(g, A.eta0, A.eta1, a, b);
+    normalise(a);
+    normalise(b);
+    R r[Y::DR + 1];
+    eliminate<R, EV, F>(a.c, b.c, r);
+    R rmax = R(0);
+    bool finite = true;
+#pragma unroll
+    for (int k = 0; k <= Y::DR; ++k) {
+        rmax = fmax(rmax, fabs(r[k]));
+        finite = finite && isfinite(r[k]);
+    }
+    if (!finite || !(rmax > R(0))) {
+        degen = 1;
+        return;
+    }
+    R rt[Y::DR + 1];
+    bool ok[Y::DR + 1];
+    isolate01<R, Y::DR>(r, rt, ok, R(A.iso_eps));
+    // FP64 coefficients of a(u, v) as a polynomial in u (u-degree TA, constant leading term)
+    P2<double, Y::TA> a64;
+    {
+        VP<double, 1> x1 = vp_affine(g.p0, g.e1, g.e2);
+        auto n = NormalPoly<double, F>::make(g);
+        VP<double, 1> d0 = x1 - vp_const(g.x0);
+        a64 = vdot(vcross(d0, vp_const(g.x2 - g.x0)), n);
+    }
+#pragma unroll
+    for (int k = 0; k <= Y::DR; ++k) {
+        if (!ok[k]) continue;
+        nvr++;
+        double v = double(rt[k]);
+        double c[Y::TA + 1];
+#pragma unroll
+        for (int i = 0; i <= Y::TA; ++i) {
+            double s = 0.0;
+#pragma unroll
+            for (int j = Y::TA - i; j >= 0; --j) s = fma(s, v, a64.c[tri_idx(Y::TA, i, j)]);
+            c[i] = s;
+        }
+        double us[2] = {0.0, 0.0};
+        int nu = 0;
+        if constexpr (Y::TA == 2) {
+            double qa = c[2], qb = c[1], qc = c[0];
+            if (qa != 0.0) {
+                double disc = qb * qb - 4.0 * qa * qc;
+                if (disc > 0.0) {
+                    double qq = -0.5 * (qb + copysign(sqrt(disc), qb));
+                    double r1 = qq / qa, r2 = qc / qq;
+                    us[0] = fmin(r1, r2);
+                    us[1] = fmax(r1, r2);
+                    nu = 2;
+                }
+            } else if (qb != 0.0) {
+                us[0] = -qc / qb;
+                nu = 1;
+            }
+        } else {
+            if (c[1] != 0.0) {
+                us[0] = -c[0] / c[1];
+                nu = 1;
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+            if (m >= nu) continue;
+            double u = us[m], vv = v;
+            if (!(u >= -A.u_margin && u <= 1.0 - v + A.u_margin)) continue;
+            ncand++;
+            if (!polish<EV>(g, A.eta0, A.eta1, A.polish_iters, u, vv)) continue;
+            if (!(u >= 0.0 && vv >= 0.0 && u + vv <= 1.0)) continue;
+            V3<double> x1 = g.p0 + g.e1 * u + g.e2 * vv;
+            V3<double> nn = g.n0 + g.dn1 * u + g.dn2 * vv;
+            double res;
+            if (!vertex_law(g.x0, x1, g.x2, nn, A.eta0, A.eta1, EV == SPOLY_T, res)) continue;
+            if (!(res <= A.tau)) continue;
+            double w = 1.0 - u - vv;
+            double edge = fmin(fmin(u, vv), w);
+            push_sol(S, u, vv, res, edge, A.dedup);
+        }
+    }
+}
+
+__device__ __forceinline__ V3<double> ld3(const double* x, const double* y, const double* z, int i)
+{
+    return {x[i], y[i], z[i]};
+}
+
+template <typename R, int EV>
+__global__ void __launch_bounds__(256) k_onebounce(OneBounceArgs A)
+{
+    const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const bool active = q < A.nq;
+    LaneSols S;
+    S.n = 0;
+    int nvr = 0, ncand = 0, degen = 0;
+    int tid = -1;
+    bool swapped = false;
+    if (active) {
+        tid = A.q_tri[q];
+        int i0 = A.tri[3 * tid], i1 = A.tri[3 * tid + 1], i2 = A.tri[3 * tid + 2];
+        V3<double> P0 = ld3(A.px, A.py, A.pz, i0), P1 = ld3(A.px, A.py, A.pz, i1), P2v = ld3(A.px, A.py, A.pz, i2);
+        V3<double> N0 = ld3(A.nx, A.ny, A.nz, i0), N1 = ld3(A.nx, A.ny, A.nz, i1), N2 = ld3(A.nx, A.ny, A.nz, i2);
+        int j0 = A.q_x0[q], j2 = A.q_x2[q];
+        Geo g;
+        g.x0 = ld3(A.x0x, A.x0y, A.x0z, j0);
+        g.x2 = ld3(A.x2x, A.x2y, A.x2z, j2);
+        g.flat = N0.x == N1.x && N0.y == N1.y && N0.z == N1.z && N0.x == N2.x && N0.y == N2.y && N0.z == N2.z;
+        V3<double> c = P0 + (P1 - P0) * (1.0 / 3.0) + (P2v - P0) * (1.0 / 3.0);
+        if constexpr (EV == SPOLY_R) swapped = pick_edge2(c, g.x0, g.x2, P1 - P0, P2v - P0);
+        if (swapped) {
+            V3<double> t = P1; P1 = P2v; P2v = t;
+            t = N1; N1 = N2; N2 = t;
+        }
+        g.p0 = P0; g.e1 = P1 - P0; g.e2 = P2v - P0;
+        g.n0 = N0; g.dn1 = N1 - N0; g.dn2 = N2 - N0;
+        g.swapped = swapped;
+        g.axis = (EV == SPOLY_T) ? pick_axis(c, g.x0, g.x2) : 0;
+        bool finite = isfinite(dot(g.p0, g.e1) + dot(g.e2, g.n0) + dot(g.dn1, g.dn2) + dot(g.x0, g.x2));
+        if (!finite) degen = 1;
+        else if (g.flat) solve_instance<R, EV, 0>(g, A, S, nvr, ncand, degen);
+        else solve_instance<R, EV, 1>(g, A, S, nvr, ncand, degen);
+    }
+    // ---- compaction: one atomic per wave, records at base + exclusive prefix
+    const int cnt = active ? S.n : 0;
+    const int incl = wave_incl_scan(cnt);
+    const int total = __shfl(incl, kWave - 1, kWave);
+    unsigned long long base = 0;
+    if (total > 0) {
+        if (lane_id() == kWave - 1) base = atomicAdd(A.out_count, (unsigned long long)total);
+        base = __shfl(base, kWave - 1, kWave);
+    }
+    const unsigned long long first = base + (unsigned long long)(incl - cnt);
+#pragma unroll
+    for (int k = 0; k < kMaxLaneSol; ++k) {
+        if (k < cnt) {
+            unsigned long long idx = first + k;
+            if (idx < (unsigned long long)A.cap) {
+                spoly_solution s;
+                s.query = int32_t(q);
+                s.tri[0] = tid;
+                s.tri[1] = -1;
+                s.flags = 0;
+                s.u[0] = swapped ? S.v[k] : S.u[k];
+                s.v[0] = swapped ? S.u[k] : S.v[k];
+                s.u[1] = 0.0;
+                s.v[1] = 0.0;
+                s.residual = float(S.res[k]);
+                s.edge = float(S.edge[k]);
+                A.out[idx] = s;
+            }
+        }
+    }
+    if (A.counters) {
+        unsigned long long s0 = wave_sum_u64(active ? nvr : 0);
+        unsigned long long s1 = wave_sum_u64(active ? ncand : 0);
+        unsigned long long s2 = wave_sum_u64(active ? degen : 0);
+        if (lane_id() == 0) {
+            if (s0) atomicAdd(A.counters + 0, s0);
+            if (s1) atomicAdd(A.counters + 1, s1);
+            if (s2) atomicAdd(A.counters + 2, s2);
+        }
+    }
+    if (A.diag_q && active) {
+        A.diag_q[2 * q] = nvr;
+        A.diag_q[2 * q + 1] = S.n;
+    }
+}
+
+hipError_t launch_onebounce(const OneBounceArgs& A, int ev, int prec, hipStream_t stream)
+{
+    if (A.nq <= 0) return hipSuccess;
+    dim3 block(256), grid(unsigned((A.nq + 255) / 256));
+    if (ev == SPOLY_R && prec == SPOLY_FP64) hipLaunchKernelGGL((k_onebounce<double, SPOLY_R>), grid, block, 0, stream, A);
+    else if (ev == SPOLY_R) hipLaunchKernelGGL((k_onebounce<float, SPOLY_R>), grid, block, 0, stream, A);
+    else if (prec == SPOLY_FP64) hipLaunchKernelGGL((k_onebounce<double, SPOLY_T>), grid, block, 0, stream, A);
+    else hipLaunchKernelGGL((k_onebounce<float, SPOLY_T>), grid, block, 0, stream, A);
+    return hipGetLastError();
+}
+
+}  // namespace spoly

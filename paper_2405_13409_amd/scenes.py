@@ -10,9 +10,11 @@ its glint and caustic workloads of Sec. 6):
 
 * ``heightfield(N, A, J, f_lo, f_hi, seed)`` -- a wavy specular surface over
   [-1,1]^2: vertices (-1+2i/N, -1+2j/N, z) with
-  z = A * sum_m sin(2 pi f_m (cos t_m x + sin t_m y) + p_m),
-  f_m ~ U[f_lo, f_hi], t_m ~ U[0, 2pi), p_m ~ U[0, 2pi) drawn (all f, then all t,
-  then all p) from ``numpy.random.default_rng(seed)``.  Vertex normals come from
+  z = A * sum_m sin(f_m (cos t_m x + sin t_m y) + p_m),
+  f_m ~ U[f_lo, f_hi] (angular frequency, radians per unit length),
+  t_m ~ U[0, 2pi), p_m ~ U[0, 2pi) drawn (all f, then all t, then all p) from
+  ``numpy.random.default_rng(seed)``.  With the grid sizes used here the
+  shortest wavelength spans about 12.6 grid cells, so each triangle is smooth.  Vertex normals come from
   the analytic gradient, normalize(-z_x, -z_y, 1); the interpolated normal of
   Eq. (eq_ni) is formed from them inside each triangle.  Cell (i, j) is split
   into (v_ij, v_i+1j, v_i+1j+1) and (v_ij, v_i+1j+1, v_ij+1), counter-clockwise
@@ -66,9 +68,9 @@ def heightfield(N: int, A: float, J: int, f_lo: float, f_hi: float, seed: int) -
     zy = np.zeros_like(X)
     for m in range(J):
         c, s = math.cos(th[m]), math.sin(th[m])
-        arg = 2.0 * math.pi * f[m] * (c * X + s * Y) + ph[m]
+        arg = f[m] * (c * X + s * Y) + ph[m]
         z += A * np.sin(arg)
-        k = A * 2.0 * math.pi * f[m] * np.cos(arg)
+        k = A * f[m] * np.cos(arg)
         zx += k * c
         zy += k * s
     P = np.stack([X.ravel(), Y.ravel(), z.ravel()], axis=1)

@@ -1,0 +1,203 @@
+"""Python binding of libspoly.so (include/spoly.h): argument marshalling only.
+
+Device memory and streams come from PyTorch; every step of the solve runs in
+the library's HIP kernels.  The library must be built (``build.py``); loading
+fails loudly otherwise.  torch is imported before the library is opened so
+that both share torch's HIP runtime.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libspoly.so")
+
+SPOLY_OK, SPOLY_E_INVALID_ARG, SPOLY_E_CAPACITY, SPOLY_E_DEVICE, SPOLY_E_UNSUPPORTED = range(5)
+SPOLY_R, SPOLY_T = 0, 1
+SPOLY_FP64, SPOLY_FP32_POLISH64 = 0, 1
+
+SOLUTION_DTYPE = np.dtype([("query", "<i4"), ("tri", "<i4", (2,)), ("flags", "<u4"), ("u", "<f8", (2,)),
+                           ("v", "<f8", (2,)), ("residual", "<f4"), ("edge", "<f4")])
+assert SOLUTION_DTYPE.itemsize == 56
+
+EXPORTED = ("spoly_ctx_create", "spoly_ctx_destroy", "spoly_default_params", "spoly_status_str",
+            "spoly_cull_1bounce", "spoly_solve_1bounce")
+
+
+class SpolyError(RuntimeError):
+    pass
+
+
+class Mesh(ctypes.Structure):
+    _fields_ = [("px", ctypes.c_void_p), ("py", ctypes.c_void_p), ("pz", ctypes.c_void_p),
+                ("nx", ctypes.c_void_p), ("ny", ctypes.c_void_p), ("nz", ctypes.c_void_p),
+                ("tri", ctypes.c_void_p), ("n_vertices", ctypes.c_int32), ("n_tris", ctypes.c_int32)]
+
+
+class Points(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p), ("n", ctypes.c_int32)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("pieces", ctypes.c_int32), ("bisect_iters", ctypes.c_int32), ("iso_eps", ctypes.c_double),
+                ("tau", ctypes.c_double), ("u_margin", ctypes.c_double), ("dedup", ctypes.c_double),
+                ("polish_iters", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Open libspoly.so (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise SpolyError(f"{path} is missing: build it with `python -m paper_2405_13409_amd.build`")
+    L = ctypes.CDLL(path)
+    P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    L.spoly_ctx_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int]
+    L.spoly_ctx_create.restype = ctypes.c_int
+    L.spoly_ctx_destroy.argtypes = [P]
+    L.spoly_ctx_destroy.restype = None
+    L.spoly_default_params.argtypes = [ctypes.POINTER(Params)]
+    L.spoly_default_params.restype = None
+    L.spoly_status_str.argtypes = [ctypes.c_int]
+    L.spoly_status_str.restype = ctypes.c_char_p
+    L.spoly_cull_1bounce.argtypes = [P, ctypes.POINTER(Mesh), ctypes.POINTER(Points), ctypes.POINTER(Points), D, D, D,
+                                     P, P, P, I64, P, P]
+    L.spoly_cull_1bounce.restype = ctypes.c_int
+    L.spoly_solve_1bounce.argtypes = [P, ctypes.POINTER(Mesh), ctypes.POINTER(Points), ctypes.POINTER(Points), P, P, P,
+                                      I64, ctypes.c_int, D, D, ctypes.c_int, ctypes.POINTER(Params), P, I64, P, P, P, P]
+    L.spoly_solve_1bounce.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(st: int, what: str):
+    if st != SPOLY_OK:
+        msg = load_library().spoly_status_str(st).decode()
+        raise SpolyError(f"{what}: {msg} ({st})")
+
+
+def default_params() -> Params:
+    p = Params()
+    load_library().spoly_default_params(ctypes.byref(p))
+    return p
+
+
+def _ptr(t: torch.Tensor | None):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class DeviceMesh:
+    """SoA mesh resident on the GPU (float64 positions / normals, int32 indices)."""
+
+    def __init__(self, P: np.ndarray, N: np.ndarray, tri: np.ndarray, device="cuda"):
+        P = np.asarray(P, dtype=np.float64)
+        N = np.asarray(N, dtype=np.float64)
+        self.cols = [torch.from_numpy(np.ascontiguousarray(P[:, k])).to(device) for k in range(3)]
+        self.cols += [torch.from_numpy(np.ascontiguousarray(N[:, k])).to(device) for k in range(3)]
+        self.tri = torch.from_numpy(np.ascontiguousarray(tri, dtype=np.int32).ravel()).to(device)
+        self.n_vertices = int(P.shape[0])
+        self.n_tris = int(len(self.tri) // 3)
+        self.c = Mesh(*[c.data_ptr() for c in self.cols], self.tri.data_ptr(), self.n_vertices, self.n_tris)
+
+
+class DevicePoints:
+    def __init__(self, X: np.ndarray, device="cuda"):
+        X = np.asarray(X, dtype=np.float64).reshape(-1, 3)
+        self.cols = [torch.from_numpy(np.ascontiguousarray(X[:, k])).to(device) for k in range(3)]
+        self.n = int(X.shape[0])
+        self.c = Points(*[c.data_ptr() for c in self.cols], self.n)
+
+
+class Context:
+    """A spoly_ctx on one device."""
+
+    def __init__(self, device: int = 0):
+        L = load_library()
+        torch.cuda.set_device(device)
+        h = ctypes.c_void_p()
+        _check(L.spoly_ctx_create(ctypes.byref(h), device), "spoly_ctx_create")
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if self.h:
+            load_library().spoly_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- S0
+    def cull_1bounce(self, mesh: DeviceMesh, x0s: DevicePoints, x2s: DevicePoints, eta0=1.0, eta1=1.0,
+                     margin=1e-3, capacity: int | None = None):
+        """Returns int32 device tensors (q_x0, q_x2, q_tri) of the kept triples."""
+        L = load_library()
+        total = x0s.n * x2s.n * mesh.n_tris
+        cap = capacity if capacity is not None else min(total, 1 << 24)
+        while True:
+            qx0 = torch.empty(cap, dtype=torch.int32, device="cuda")
+            qx2 = torch.empty(cap, dtype=torch.int32, device="cuda")
+            qt = torch.empty(cap, dtype=torch.int32, device="cuda")
+            cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+            _check(L.spoly_cull_1bounce(self.h, ctypes.byref(mesh.c), ctypes.byref(x0s.c), ctypes.byref(x2s.c),
+                                        eta0, eta1, margin, _ptr(qx0), _ptr(qx2), _ptr(qt), cap, _ptr(cnt),
+                                        _stream()), "spoly_cull_1bounce")
+            n = int(cnt.item())
+            if n <= cap:
+                return qx0[:n], qx2[:n], qt[:n]
+            cap = n
+
+    # ---------------------------------------------------------------- S1-S7
+    def solve_1bounce(self, mesh: DeviceMesh, x0s: DevicePoints, x2s: DevicePoints, q_x0: torch.Tensor,
+                      q_x2: torch.Tensor, q_tri: torch.Tensor, event: str, eta0=1.0, eta1=1.0,
+                      precision: int = SPOLY_FP64, params: Params | None = None, capacity: int | None = None,
+                      counters: torch.Tensor | None = None, diag: torch.Tensor | None = None,
+                      out: torch.Tensor | None = None, out_count: torch.Tensor | None = None, sync: bool = True):
+        """Enqueue the solve.  With sync=True returns the solutions as a numpy
+        structured array (SOLUTION_DTYPE), re-running once with a larger buffer
+        on overflow."""
+        L = load_library()
+        nq = int(q_tri.numel())
+        prm = params or default_params()
+        cap = capacity if capacity is not None else max(1024, nq // 4)
+        ev = SPOLY_T if event == "T" else SPOLY_R
+        while True:
+            buf = out if out is not None else torch.empty(cap * SOLUTION_DTYPE.itemsize, dtype=torch.uint8,
+                                                          device="cuda")
+            cnt = out_count if out_count is not None else torch.zeros(1, dtype=torch.int64, device="cuda")
+            if out_count is not None:
+                cnt.zero_()
+            _check(L.spoly_solve_1bounce(self.h, ctypes.byref(mesh.c), ctypes.byref(x0s.c), ctypes.byref(x2s.c),
+                                         _ptr(q_x0), _ptr(q_x2), _ptr(q_tri), nq, ev, eta0, eta1, precision,
+                                         ctypes.byref(prm), _ptr(buf), buf.numel() // SOLUTION_DTYPE.itemsize,
+                                         _ptr(cnt), _ptr(counters), _ptr(diag), _stream()), "spoly_solve_1bounce")
+            if not sync:
+                return buf, cnt
+            n = int(cnt.item())
+            capn = buf.numel() // SOLUTION_DTYPE.itemsize
+            if n <= capn:
+                host = buf[: n * SOLUTION_DTYPE.itemsize].cpu().numpy()
+                return host.view(SOLUTION_DTYPE)
+            if out is not None:
+                raise SpolyError(f"output capacity {capn} < {n} solutions")
+            cap = n
+
+
+def sort_solutions(s: np.ndarray) -> np.ndarray:
+    """Deterministic order: by (query, v, u) of the first vertex."""
+    return s[np.lexsort((s["u"][:, 0], s["v"][:, 0], s["query"]))]

@@ -1,0 +1,199 @@
+"""GPU parity of the one-vertex path (S0-S7) against the FP64 oracle, through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import parity
+from paper_2405_13409_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sp():
+    from paper_2405_13409_amd import spoly
+
+    spoly.load_library()
+    return spoly
+
+
+@pytest.fixture(scope="module")
+def ctx(sp):
+    c = sp.Context(0)
+    yield c
+    c.close()
+
+
+def _run(sp, ctx, mesh, x0s, x2s, q0, q2, qt, ev, eta0, eta1, prec, diag=False):
+    dm = sp.DeviceMesh(mesh.P, mesh.N, mesh.tri)
+    d0, d2 = sp.DevicePoints(x0s), sp.DevicePoints(x2s)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).cuda()  # noqa: E731
+    cnt = torch.zeros(4, dtype=torch.int64, device="cuda")
+    dq = torch.zeros(2 * len(qt), dtype=torch.int32, device="cuda") if diag else None
+    sols = ctx.solve_1bounce(dm, d0, d2, t(q0), t(q2), t(qt), ev, eta0, eta1, prec, counters=cnt, diag=dq)
+    torch.cuda.synchronize()
+    return sols, cnt.cpu().numpy(), (dq.cpu().numpy().reshape(-1, 2) if diag else None)
+
+
+def _tag(name):
+    print(f"[gpu-case] {name}", flush=True)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_small_glints_reflection_parity(sp, ctx, prec):
+    _tag(f"small glints R prec={prec}")
+    w = scenes.glints_small()
+    orc, diag = oracle.solve_1bounce(w.mesh.P, w.mesh.N, w.mesh.tri, w.x0, w.x2, w.q_x0, w.q_x2, w.q_tri, "R")
+    sols, cnt, dq = _run(sp, ctx, w.mesh, w.x0, w.x2, w.q_x0, w.q_x2, w.q_tri, "R", 1.0, 1.0, prec, diag=True)
+    st = parity.compare_onebounce(sols, orc, diag, len(w.q_tri), **(parity.FP64 if prec == 0 else parity.FP32))
+    print(st)
+    assert st["compared"] > 3000
+    assert st["ambiguous_fraction"] < 0.01
+    assert cnt[2] == 0  # no degenerate instance
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_small_glints_refraction_parity(sp, ctx, prec):
+    _tag(f"small glints T prec={prec}")
+    w = scenes.glints_small()
+    x0 = w.x0.copy()
+    x0[:, 2] = -1.0
+    orc, diag = oracle.solve_1bounce(w.mesh.P, w.mesh.N, w.mesh.tri, x0, w.x2, w.q_x0, w.q_x2, w.q_tri, "T", 1.5, 1.0)
+    sols, cnt, _ = _run(sp, ctx, w.mesh, x0, w.x2, w.q_x0, w.q_x2, w.q_tri, "T", 1.5, 1.0, prec)
+    st = parity.compare_onebounce(sols, orc, diag, len(w.q_tri), **(parity.FP64 if prec == 0 else parity.FP32))
+    print(st)
+    assert st["compared"] > 100
+
+
+def test_flat_triangles_mirror_and_snell(sp, ctx):
+    _tag("flat triangles")
+    rng = np.random.default_rng(11)
+    nt = 300
+    P = rng.uniform(-1, 1, (nt * 3, 3))
+    tri = np.arange(nt * 3, dtype=np.int32).reshape(nt, 3)
+    N = np.zeros_like(P)
+    for t in range(nt):
+        m = np.cross(P[3 * t + 1] - P[3 * t], P[3 * t + 2] - P[3 * t])
+        m /= np.linalg.norm(m)
+        if m[2] < 0:
+            m = -m
+        N[3 * t:3 * t + 3] = m
+    x0 = rng.uniform(-1, 1, (8, 3)) + np.array([0, 0, 3.0])
+    x2 = np.array([[0.2, -0.1, 3.5], [0.1, 0.3, -3.0]])
+    q0, qt = scenes.all_pairs(len(x0), nt)
+    for ev, j2, e0, e1 in (("R", 0, 1.0, 1.0), ("T", 1, 1.0, 1.33)):
+        q2 = np.full_like(q0, j2)
+        orc, diag = oracle.solve_1bounce(P, N, tri, x0, x2, q0, q2, qt, ev, e0, e1)
+        sols, cnt, _ = _run(sp, ctx, scenes.Mesh(P, N, tri), x0, x2, q0, q2, qt, ev, e0, e1, 0)
+        st = parity.compare_onebounce(sols, orc, diag, len(qt), **parity.FP64)
+        print(ev, st)
+        assert st["compared"] > 10
+
+
+def test_capacity_overflow_and_empty(sp, ctx):
+    _tag("capacity / empty")
+    w = scenes.glints_small()
+    dm = sp.DeviceMesh(w.mesh.P, w.mesh.N, w.mesh.tri)
+    d0, d2 = sp.DevicePoints(w.x0), sp.DevicePoints(w.x2)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).cuda()  # noqa: E731
+    q0, q2, qt = t(w.q_x0), t(w.q_x2), t(w.q_tri)
+    out = torch.zeros(10 * sp.SOLUTION_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    ctx.solve_1bounce(dm, d0, d2, q0, q2, qt, "R", out=out, out_count=cnt, sync=False)
+    torch.cuda.synchronize()
+    n = int(cnt.item())
+    assert n > 10
+    rec = out.cpu().numpy().view(sp.SOLUTION_DTYPE)
+    assert np.all(rec["tri"][:, 0] >= 0) and np.all(rec["query"] >= 0)
+    full = ctx.solve_1bounce(dm, d0, d2, q0, q2, qt, "R")
+    assert len(full) == n
+    # zero queries
+    e = ctx.solve_1bounce(dm, d0, d2, q0[:0], q2[:0], qt[:0], "R")
+    assert len(e) == 0
+
+
+def test_degenerate_and_nonfinite_inputs(sp, ctx):
+    _tag("degenerate inputs")
+    P = np.array([[0, 0, 0], [1, 0, 0], [2, 0, 0], [0, 0, 0], [1, 0, 0], [0, 1, 0.0]])
+    N = np.array([[0, 0, 1.0]] * 6)
+    N[5] = [np.nan, 0, 1]
+    tri = np.array([[0, 1, 2], [3, 4, 5]], dtype=np.int32)
+    x0 = np.array([[0.3, 0.2, 1.0]])
+    x2 = np.array([[0.1, 0.1, 2.0]])
+    sols, cnt, _ = _run(sp, ctx, scenes.Mesh(P, N, tri), x0, x2, [0, 0], [0, 0], [0, 1], "R", 1.0, 1.0, 0)
+    assert len(sols) == 0
+    assert cnt[2] >= 1
+
+
+def test_determinism(sp, ctx):
+    _tag("determinism")
+    w = scenes.glints_small()
+    a, _, _ = _run(sp, ctx, w.mesh, w.x0, w.x2, w.q_x0, w.q_x2, w.q_tri, "R", 1.0, 1.0, 1)
+    b, _, _ = _run(sp, ctx, w.mesh, w.x0, w.x2, w.q_x0, w.q_x2, w.q_tri, "R", 1.0, 1.0, 1)
+    a, b = sp.sort_solutions(a), sp.sort_solutions(b)
+    assert a.tobytes() == b.tobytes()
+
+
+# ------------------------------------------------------------------ config 2: cull + solve
+
+def _cull_gpu(sp, ctx, mesh, x0, x2, e0, e1, margin=1e-3):
+    dm = sp.DeviceMesh(mesh.P, mesh.N, mesh.tri)
+    d0, d2 = sp.DevicePoints(x0), sp.DevicePoints(x2)
+    q0, q2, qt = ctx.cull_1bounce(dm, d0, d2, e0, e1, margin)
+    torch.cuda.synchronize()
+    return q0.cpu().numpy(), q2.cpu().numpy(), qt.cpu().numpy()
+
+
+@pytest.mark.parametrize("ev", ["R", "T"])
+def test_cull_bounds_against_oracle_twin(sp, ctx, ev):
+    _tag(f"cull {ev}")
+    mesh = scenes.glints_large_mesh()
+    x0 = scenes.glints_large_points(ev)[::512]
+    x2 = scenes.GLINTS_LARGE_LIGHT
+    e0, e1 = (1.0, 1.0) if ev == "R" else (1.5, 1.0)
+    q0, q2, qt = _cull_gpu(sp, ctx, mesh, x0, x2, e0, e1, 1e-3)
+    g = np.zeros((len(x0), 1, mesh.nt), dtype=bool)
+    g[q0, q2, qt] = True
+    assert len(q0) == g.sum()  # no duplicates
+    k_tight = oracle.cull_1bounce(mesh.P, mesh.N, mesh.tri, x0, x2, e0, e1, 0.0)
+    k_loose = oracle.cull_1bounce(mesh.P, mesh.N, mesh.tri, x0, x2, e0, e1, 3e-3)
+    assert np.all(g[k_tight]), "GPU cull dropped a triple the FP64 twin keeps"
+    assert np.all(k_loose[g]), "GPU cull kept a triple outside the widened FP64 twin"
+
+
+@pytest.mark.parametrize("ev", ["R", "T"])
+def test_cull_is_conservative(sp, ctx, ev):
+    """Among sampled triples the cull rejects, the oracle finds no admissible path."""
+    _tag(f"cull conservative {ev}")
+    mesh = scenes.glints_large_mesh()
+    x0 = scenes.glints_large_points(ev)[::4096]
+    x2 = scenes.GLINTS_LARGE_LIGHT
+    e0, e1 = (1.0, 1.0) if ev == "R" else (1.5, 1.0)
+    q0, q2, qt = _cull_gpu(sp, ctx, mesh, x0, x2, e0, e1, 1e-3)
+    g = np.zeros((len(x0), mesh.nt), dtype=bool)
+    g[q0, qt] = True
+    rej0, rejt = np.nonzero(~g)
+    rng = np.random.default_rng(5)
+    s = rng.choice(len(rej0), min(len(rej0), 60000), replace=False)
+    orc, _ = oracle.solve_1bounce(mesh.P, mesh.N, mesh.tri, x0, x2, rej0[s], np.zeros(len(s)), rejt[s], ev, e0, e1)
+    assert len(orc) == 0
+
+
+@pytest.mark.parametrize("ev", ["R", "T"])
+def test_large_glints_sample_parity_fp32(sp, ctx, ev):
+    _tag(f"large glints sample {ev}")
+    mesh = scenes.glints_large_mesh()
+    x0 = scenes.glints_large_points(ev)[::64]
+    x2 = scenes.GLINTS_LARGE_LIGHT
+    e0, e1 = (1.0, 1.0) if ev == "R" else (1.5, 1.0)
+    q0, q2, qt = _cull_gpu(sp, ctx, mesh, x0, x2, e0, e1, 1e-3)
+    rng = np.random.default_rng(7)
+    s = np.sort(rng.choice(len(q0), min(len(q0), 150000), replace=False))
+    q0, q2, qt = q0[s], q2[s], qt[s]
+    orc, diag = oracle.solve_1bounce(mesh.P, mesh.N, mesh.tri, x0, x2, q0, q2, qt, ev, e0, e1)
+    for prec, tol in ((1, parity.FP32), (0, parity.FP64)):
+        sols, cnt, _ = _run(sp, ctx, mesh, x0, x2, q0, q2, qt, ev, e0, e1, prec)
+        st = parity.compare_onebounce(sols, orc, diag, len(qt), **tol)
+        print(ev, prec, st)
+        assert st["compared"] > 50
