@@ -166,6 +166,49 @@ spoly_status spoly_solve_1bounce(spoly_ctx *ctx, const spoly_mesh *mesh,
                                  unsigned long long *out_count, unsigned long long *counters,
                                  int32_t *diag_q, void *stream);
 
+/*
+ * S0 for two specular vertices (chain x0 -> T1 -> T2 -> x3).
+ * For every x0 in x0s, x3 in x3s and ordered pair of distinct triangles, keep
+ * the tuple unless one vertex fails the half-vector / normal-cone test of
+ * spoly_cull_1bounce: at x1 the half vector combines the direction to x0
+ * (eta[0]) with the direction cone from T1's bounding sphere to T2's (eta[1]);
+ * at x2 the cone from T2 to T1 (eta[1]) with the direction to x3 (eta[2]).
+ * The test at x2 does not depend on x0: it is evaluated once per (light, T1,
+ * T2) into a pair list held in the context, then every x0 is tested against
+ * the listed pairs.  eta [host, 3].  Output: int32 arrays out_x0, out_x3,
+ * out_t1, out_t2 [out_capacity]; *out_count (device uint64, zeroed by the
+ * caller) receives the total kept.  Synchronises `stream` once per light
+ * (to size the second pass).
+ */
+spoly_status spoly_cull_2bounce(spoly_ctx *ctx, const spoly_mesh *mesh,
+                                const spoly_points *x0s, const spoly_points *x3s,
+                                const double *eta, double margin,
+                                int32_t *out_x0, int32_t *out_x3, int32_t *out_t1, int32_t *out_t2,
+                                int64_t out_capacity, unsigned long long *out_count, void *stream);
+
+/*
+ * S1-S7 for k = 2 specular vertices (Sec. 4.4-4.5, Sec. 5.2): chain [host, k]
+ * must be {SPOLY_T, SPOLY_T}; eta [host, k+1] = IORs of the segments x0x1,
+ * x1x2, x2x3 (Eq. eq_ch).  Query q solves x0s[q_x0[q]] -> triangle q_tris[2q]
+ * -> triangle q_tris[2q+1] -> x3s[q_x3[q]].
+ * The refracted direction at x1 uses the piecewise (1,1)-rational square root of
+ * Sec. 4.4: sqrt_table [host, optional] = 7 piece ends then (c0, c1, d0, d1)
+ * for each of the 6 pieces; NULL selects the library's minimax table.  The
+ * sign of det R(v) is sampled at v = j/pieces (pieces <= 127) and each sign
+ * change is bisected bisect_iters times; every candidate is polished in FP64 on
+ * the exact refraction constraints (the approximation only brackets roots).
+ * prec must be SPOLY_FP64.  Records carry tri[0..1] and (u,v) of both vertices.
+ * counters / diag_q as for spoly_solve_1bounce ([0] counts sign changes).
+ */
+spoly_status spoly_solve_nbounce(spoly_ctx *ctx, const spoly_mesh *mesh, int32_t k,
+                                 const spoly_event *chain, const double *eta,
+                                 const spoly_points *x0s, const spoly_points *x3s,
+                                 const int32_t *q_x0, const int32_t *q_x3, const int32_t *q_tris,
+                                 int64_t n_queries, spoly_precision prec, const spoly_params *params,
+                                 const double *sqrt_table,
+                                 spoly_solution *out, int64_t out_capacity, unsigned long long *out_count,
+                                 unsigned long long *counters, int32_t *diag_q, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -27,7 +27,7 @@ F_DEGENERATE, F_EDGE2, F_AXIS_Z, F_AXIS_Y, F_FLAT1, F_FLAT2 = 1, 2, 4, 8, 16, 32
 class Params(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_double), ("u_margin", ctypes.c_double), ("dedup", ctypes.c_double),
                 ("polish_iters", ctypes.c_int32), ("pieces", ctypes.c_int32),
-                ("bisect_iters", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("bisect_iters", ctypes.c_int32), ("det_method", ctypes.c_int32)]
 
 
 class SqrtFit(ctypes.Structure):
@@ -39,7 +39,7 @@ def default_params(two_bounce: bool = False) -> Params:
     bisection steps (Sec. 5.2); u searched on [-m, 1-v+m] before polish with
     m = 1e-4 (one bounce) or 0.05 (two bounces, whose approximate roots can sit
     up to ~1e-2 away from the exact ones); up to 6 Newton steps."""
-    return Params(1e-6, 0.05 if two_bounce else 1e-4, 1e-8, 6, 100, 10, 0)
+    return Params(1e-6, 0.05 if two_bounce else 1e-4, 1e-8, 6, 100, 10, 1 if two_bounce else 0)
 
 
 def build(force: bool = False) -> str:
@@ -70,6 +70,8 @@ def lib():
         L.or_isolate.argtypes = [P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, P, ctypes.c_int32]
         L.or_det_sign.argtypes = [P, ctypes.c_int32, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double]
         L.or_maxsol.restype = ctypes.c_int
+        L.or_cull_tt.argtypes = [P, P, P, ctypes.c_int64, P, ctypes.c_int64, P, ctypes.c_int64, P,
+                                 ctypes.c_double, P]
         L.or_cull_1bounce.argtypes = [P, P, P, ctypes.c_int64, P, ctypes.c_int64, P, ctypes.c_int64,
                                       ctypes.c_double, ctypes.c_double, ctypes.c_double, P]
         _lib = L
@@ -222,3 +224,15 @@ def cull_1bounce(P, N, tri, x0s, x2s, eta0=1.0, eta1=1.0, margin=0.0) -> np.ndar
     keep = np.zeros(n0 * n2 * nt, dtype=np.uint8)
     L.or_cull_1bounce(_p(P), _p(N), _p(tri), nt, _p(x0s), n0, _p(x2s), n2, eta0, eta1, margin, _p(keep))
     return keep.reshape(n0, n2, nt).astype(bool)
+
+
+def cull_tt(P, N, tri, x0s, x3s, eta=(1.0, 1.5, 1.0), margin=0.0) -> np.ndarray:
+    """Keep mask [n0, n3, nt, nt] (bool) of the FP64 two-vertex cone cull."""
+    L = lib()
+    P, N, x0s, x3s = (_c(a, np.float64) for a in (P, N, x0s, x3s))
+    tri = _c(tri, np.int32)
+    eta = _c(eta, np.float64)
+    n0, n3, nt = len(x0s), len(x3s), len(tri)
+    keep = np.zeros(n0 * n3 * nt * nt, dtype=np.uint8)
+    L.or_cull_tt(_p(P), _p(N), _p(tri), nt, _p(x0s), n0, _p(x3s), n3, _p(eta), margin, _p(keep))
+    return keep.reshape(n0, n3, nt, nt).astype(bool)

@@ -49,7 +49,8 @@ typedef struct {
     int32_t polish_iters;/* max Newton iterations of the polish                         */
     int32_t pieces;      /* uniform pieces of [0,1] for the >=2-bounce scan (100)       */
     int32_t bisect_iters;/* bisection steps per sign change (10)                        */
-    int32_t pad;
+    int32_t det_method;  /* sign of det R(v): 0 Gaussian elimination on the Bezout matrix, */
+                         /* 1 product formula over the real roots of a(.,v)              */
 } or_params;
 
 typedef struct {
@@ -846,6 +847,54 @@ static int polish_tt(const tri_t *T1, const tri_t *T2, v3 x0, v3 x3, const doubl
     return step <= 1e-10;
 }
 
+
+/* Sign of det R(v) through the resultant's product formula.  With
+ * det R(v) = C lc_u(b)^(n - deg a) Res_u(a, b) (C a nonzero constant) and
+ * Res_u(a, b) = lc_u(a)^(deg b) prod_{a(alpha)=0} b(alpha), where complex
+ * conjugate roots contribute |b(alpha)|^2 > 0, the sign of det R(v) is, up to
+ * the constant sign of C lc(b)^(n - deg a) (lc(b) is a constant for the TT
+ * system), sgn(lc(a))^(deg b) times the product of sgn b(alpha) over the REAL
+ * roots alpha of a(., v).  The real roots are isolated (Sec. 5.2 isolation) on
+ * [-B, B] with B = 2 max_k |a_{m-k}/a_m|^(1/k) (Fujiwara's bound on every root),
+ * in the scaled variable w = u/B.                                            */
+static int res_sign_product(arena *A, bp a, int ma, bp b, int n, double v)
+{
+    size_t mark = A->top;
+    double *ai = (double *)ar_alloc(A, sizeof(double) * (size_t)(ma + 1));
+    double *bi = (double *)ar_alloc(A, sizeof(double) * (size_t)(b.d + 1));
+    for (int i = 0; i <= ma; ++i) {
+        double s = 0.0;
+        for (int j = a.d - i; j >= 0; --j) s = s * v + a.c[i * (a.d + 1) + j];
+        ai[i] = s;
+    }
+    for (int i = 0; i <= b.d; ++i) {
+        double s = 0.0;
+        for (int j = b.d - i; j >= 0; --j) s = s * v + b.c[i * (b.d + 1) + j];
+        bi[i] = s;
+    }
+    /* the structural u-degree of b is even for the TT system (6D + 2 + 2 f2), so
+     * sgn(lc(a))^(deg b) = +1 */
+    int sign = 1;
+    (void)n;
+    if (ai[ma] == 0.0) { A->top = mark; return 1; }
+    double B = 0.0;
+    for (int k = 1; k <= ma; ++k) B = fmax(B, pow(fabs(ai[ma - k] / ai[ma]), 1.0 / k));
+    B = 2.0 * B;
+    if (!(B > 0.0)) B = 1.0;
+    double *w = (double *)ar_alloc(A, sizeof(double) * (size_t)(ma + 1));
+    double pw = 1.0;
+    for (int k = 0; k <= ma; ++k) { w[k] = ai[k] * pw; pw *= B; }
+    double roots[64];
+    int nr = isolate(A, w, ma, -1.0, 1.0, roots, 64);
+    for (int k = 0; k < nr; ++k) {
+        double al = roots[k] * B, s = 0.0;
+        for (int i = b.d; i >= 0; --i) s = s * al + bi[i];
+        if (s < 0.0) sign = -sign;
+    }
+    A->top = mark;
+    return sign;
+}
+
 static void solve_tt(arena *A, const tri_t *T1, const tri_t *T2, v3 x0, v3 x3, const double *eta,
                      const or_sqrtfit *fit, const or_params *prm, int32_t qid,
                      or_sol *out, int32_t *nout, or_diag *dg)
@@ -863,7 +912,8 @@ static void solve_tt(arena *A, const tri_t *T1, const tri_t *T2, v3 x0, v3 x3, c
     /* piecewise sign scan of det R(v) on [0,1] */
     int P = prm->pieces;
     int *sg = (int *)ar_alloc(A, sizeof(int) * (size_t)(P + 1));
-    for (int j = 0; j <= P; ++j) sg[j] = det_sign_at(A, a, b, n, (double)j / P);
+#define DETSIGN(vv) (prm->det_method == 1 ? res_sign_product(A, a, ma, b, n, (vv)) : det_sign_at(A, a, b, n, (vv)))
+    for (int j = 0; j <= P; ++j) sg[j] = DETSIGN((double)j / P);
     double vr[OR_MAXSOL * 8];
     int nv = 0;
     for (int j = 0; j < P; ++j) {
@@ -872,7 +922,7 @@ static void solve_tt(arena *A, const tri_t *T1, const tri_t *T2, v3 x0, v3 x3, c
         int sl = sg[j];
         for (int it = 0; it < prm->bisect_iters; ++it) {
             double m = 0.5 * (l + r);
-            if (det_sign_at(A, a, b, n, m) == sl) l = m; else r = m;
+            if (DETSIGN(m) == sl) l = m; else r = m;
         }
         if (nv < OR_MAXSOL * 8) vr[nv++] = 0.5 * (l + r);
     }
@@ -1017,5 +1067,83 @@ int or_cull_1bounce(const double *P, const double *N, const int32_t *tri, int64_
                 keep[(j0 * n2 + j2) * nt + t] = (uint8_t)k;
             }
     }
+    return 0;
+}
+
+/* ================================================================== S0 twin for two vertices (FP64)
+ * Tuple (x0, T1, T2, x3) is kept unless one of the two vertices fails the
+ * half-vector / normal-cone test of or_cull_1bounce: at x1 the directions go to
+ * x0 (eta[0]) and into the cone from T1 to T2 (eta[1]); at x2 they go into
+ * the cone from T2 to T1 (eta[1]) and to x3 (eta[2]).  The cone between the
+ * bounding spheres of two triangles has axis c_b - c_a and half angle
+ * asin((r_a + r_b)/|c_b - c_a|).  keep: [n0, n3, nt, nt] bytes.            */
+typedef struct { v3 c, an; double rad, thn; int ok; } or_cone;
+
+static or_cone tri_cone(const double *P, const double *N, const int32_t *tri, int64_t t)
+{
+    or_cone k;
+    v3 p[3], n[3];
+    for (int j = 0; j < 3; ++j) { p[j] = vload(P, tri[3 * t + j]); n[j] = vnorm(vload(N, tri[3 * t + j])); }
+    k.c = vmul(vadd(vadd(p[0], p[1]), p[2]), 1.0 / 3.0);
+    k.rad = fmax(fmax(vlen(vsub(p[0], k.c)), vlen(vsub(p[1], k.c))), vlen(vsub(p[2], k.c)));
+    v3 an = vadd(vadd(n[0], n[1]), n[2]);
+    k.ok = vlen(an) > 0.5;
+    k.an = vnorm(an);
+    k.thn = 0.0;
+    for (int j = 0; j < 3; ++j) k.thn = fmax(k.thn, acos(fmin(1.0, fmax(-1.0, vdot(k.an, n[j])))));
+    return k;
+}
+
+/* direction cone (axis a, chord bound ch = 2 sin(theta/2)); returns 0 if unbounded */
+static int dir_cone(v3 from, double r, v3 to, double *ch, v3 *a)
+{
+    v3 d = vsub(to, from);
+    double l = vlen(d);
+    if (!(l > r)) return 0;
+    *a = vmul(d, 1.0 / l);
+    double s = r / l;
+    *ch = sqrt(fmax(0.0, 2.0 - 2.0 * sqrt(fmax(0.0, 1.0 - s * s))));
+    return 1;
+}
+
+static int vertex_cone_keep(const or_cone *k, v3 aa, double cha, double ea, v3 ab, double chb, double eb, double margin)
+{
+    if (!k->ok || !(k->thn < M_PI / 2)) return 1;
+    v3 H = vadd(vmul(aa, ea), vmul(ab, eb));
+    double L = vlen(H), delta = ea * cha + eb * chb;
+    if (!(delta < L)) return 1;
+    double lim = k->thn + asin(delta / L) + margin;
+    if (lim >= M_PI / 2) return 1;
+    return fabs(vdot(k->an, H)) / L >= cos(lim);
+}
+
+int or_cull_tt(const double *P, const double *N, const int32_t *tri, int64_t nt,
+               const double *x0s, int64_t n0, const double *x3s, int64_t n3,
+               const double *eta, double margin, uint8_t *keep)
+{
+    or_cone *K = (or_cone *)malloc(sizeof(or_cone) * (size_t)nt);
+    for (int64_t t = 0; t < nt; ++t) K[t] = tri_cone(P, N, tri, t);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t t1 = 0; t1 < nt; ++t1)
+        for (int64_t t2 = 0; t2 < nt; ++t2)
+            for (int64_t j0 = 0; j0 < n0; ++j0)
+                for (int64_t j3 = 0; j3 < n3; ++j3) {
+                    uint8_t k = 0;
+                    if (t1 != t2) {
+                        const or_cone *A1 = &K[t1], *A2 = &K[t2];
+                        v3 x0 = vload(x0s, j0), x3 = vload(x3s, j3);
+                        double ch0, ch12, ch21, ch3;
+                        v3 a0, a12, a21, a3;
+                        int b0 = dir_cone(A1->c, A1->rad, x0, &ch0, &a0);
+                        int b12 = dir_cone(A1->c, A1->rad + A2->rad, A2->c, &ch12, &a12);
+                        int b21 = dir_cone(A2->c, A1->rad + A2->rad, A1->c, &ch21, &a21);
+                        int b3 = dir_cone(A2->c, A2->rad, x3, &ch3, &a3);
+                        int k1 = (b0 && b12) ? vertex_cone_keep(A1, a0, ch0, eta[0], a12, ch12, eta[1], margin) : 1;
+                        int k2 = (b21 && b3) ? vertex_cone_keep(A2, a21, ch21, eta[1], a3, ch3, eta[2], margin) : 1;
+                        k = (uint8_t)(k1 && k2);
+                    }
+                    keep[((j0 * n3 + j3) * nt + t1) * nt + t2] = k;
+                }
+    free(K);
     return 0;
 }

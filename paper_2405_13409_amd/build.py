@@ -1,7 +1,8 @@
 """Build libspoly.so (gfx950) in-tree with hipcc.
 
-The elimination phase of the one-vertex kernels is generated code
-(csrc/gen_laplace.py -> csrc/laplace_gen.inc); it is regenerated on every build.
+Two sources are generated on every build: the elimination phase of the
+one-vertex kernels (csrc/gen_laplace.py -> csrc/laplace_gen.inc) and the
+square-root approximation table (sqrtfit.py -> csrc/sqrt_table.inc).
 """
 from __future__ import annotations
 
@@ -26,13 +27,18 @@ HIP_FLAGS = [
 ]
 
 
+def _write_if_changed(path: str, data: bytes) -> None:
+    old = open(path, "rb").read() if os.path.exists(path) else b""
+    if old != data:
+        with open(path, "wb") as f:
+            f.write(data)
+
+
 def generate() -> None:
     out = subprocess.check_output([sys.executable, os.path.join(CSRC, "gen_laplace.py")])
-    path = os.path.join(CSRC, "laplace_gen.inc")
-    old = open(path, "rb").read() if os.path.exists(path) else b""
-    if old != out:
-        with open(path, "wb") as f:
-            f.write(out)
+    _write_if_changed(os.path.join(CSRC, "laplace_gen.inc"), out)
+    out = subprocess.check_output([sys.executable, os.path.join(HERE, "sqrtfit.py")])
+    _write_if_changed(os.path.join(CSRC, "sqrt_table.inc"), out)
 
 
 def sources():

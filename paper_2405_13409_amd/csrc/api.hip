@@ -7,11 +7,16 @@
 
 #include "../../include/spoly.h"
 #include "onebounce.hpp"
+#include "twobounce.hpp"
+#include "sqrt_table.inc"
 
 struct spoly_ctx {
     int device;
     float4* tri_cone;      // 2 float4 per triangle, grown on demand
     int64_t tri_cone_cap;  // in triangles
+    int2* pairs;           // two-vertex cull: (T1, T2) pairs of one light
+    int64_t pairs_cap;
+    unsigned long long* pair_count;
 };
 
 namespace {
@@ -71,7 +76,22 @@ void spoly_ctx_destroy(spoly_ctx* ctx)
 {
     if (!ctx) return;
     if (ctx->tri_cone) (void)hipFree(ctx->tri_cone);
+    if (ctx->pairs) (void)hipFree(ctx->pairs);
+    if (ctx->pair_count) (void)hipFree(ctx->pair_count);
     std::free(ctx);
+}
+
+static spoly_status ensure_cones(spoly_ctx* ctx, const spoly_mesh* mesh, hipStream_t s)
+{
+    if (ctx->tri_cone_cap < mesh->n_tris) {
+        if (ctx->tri_cone) (void)hipFree(ctx->tri_cone);
+        ctx->tri_cone = nullptr;
+        ctx->tri_cone_cap = 0;
+        if (hipMalloc(&ctx->tri_cone, sizeof(float4) * 2 * size_t(mesh->n_tris)) != hipSuccess) return SPOLY_E_DEVICE;
+        ctx->tri_cone_cap = mesh->n_tris;
+    }
+    return dev_err(spoly::launch_tri_cones(mesh->px, mesh->py, mesh->pz, mesh->nx, mesh->ny, mesh->nz, mesh->tri,
+                                           mesh->n_tris, ctx->tri_cone, s));
 }
 
 spoly_status spoly_cull_1bounce(spoly_ctx* ctx, const spoly_mesh* mesh, const spoly_points* x0s,
@@ -84,16 +104,8 @@ spoly_status spoly_cull_1bounce(spoly_ctx* ctx, const spoly_mesh* mesh, const sp
     if (!(eta0 > 0.0) || !(eta1 > 0.0) || !(margin >= 0.0)) return SPOLY_E_INVALID_ARG;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (hipSetDevice(ctx->device) != hipSuccess) return SPOLY_E_DEVICE;
-    if (ctx->tri_cone_cap < mesh->n_tris) {
-        if (ctx->tri_cone) (void)hipFree(ctx->tri_cone);
-        ctx->tri_cone = nullptr;
-        ctx->tri_cone_cap = 0;
-        if (hipMalloc(&ctx->tri_cone, sizeof(float4) * 2 * size_t(mesh->n_tris)) != hipSuccess) return SPOLY_E_DEVICE;
-        ctx->tri_cone_cap = mesh->n_tris;
-    }
-    hipError_t e = spoly::launch_tri_cones(mesh->px, mesh->py, mesh->pz, mesh->nx, mesh->ny, mesh->nz, mesh->tri,
-                                           mesh->n_tris, ctx->tri_cone, s);
-    if (e != hipSuccess) return SPOLY_E_DEVICE;
+    spoly_status st = ensure_cones(ctx, mesh, s);
+    if (st != SPOLY_OK) return st;
     spoly::CullArgs A;
     A.tri_cone = ctx->tri_cone;
     A.n_tris = mesh->n_tris;
@@ -138,6 +150,93 @@ spoly_status spoly_solve_1bounce(spoly_ctx* ctx, const spoly_mesh* mesh, const s
     A.out = out; A.cap = out_capacity; A.out_count = out_count;
     A.counters = counters; A.diag_q = diag_q;
     return dev_err(spoly::launch_onebounce(A, int(ev), int(prec), static_cast<hipStream_t>(stream)));
+}
+
+}  // extern "C"
+
+extern "C" {
+
+spoly_status spoly_cull_2bounce(spoly_ctx* ctx, const spoly_mesh* mesh, const spoly_points* x0s,
+                                const spoly_points* x3s, const double* eta, double margin, int32_t* out_x0,
+                                int32_t* out_x3, int32_t* out_t1, int32_t* out_t2, int64_t out_capacity,
+                                unsigned long long* out_count, void* stream)
+{
+    if (!ctx || !mesh_ok(mesh) || !pts_ok(x0s) || !pts_ok(x3s) || !eta || !out_count || out_capacity < 0)
+        return SPOLY_E_INVALID_ARG;
+    if (out_capacity > 0 && (!out_x0 || !out_x3 || !out_t1 || !out_t2)) return SPOLY_E_INVALID_ARG;
+    if (!(eta[0] > 0.0) || !(eta[1] > 0.0) || !(eta[2] > 0.0) || !(margin >= 0.0)) return SPOLY_E_INVALID_ARG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (hipSetDevice(ctx->device) != hipSuccess) return SPOLY_E_DEVICE;
+    spoly_status st = ensure_cones(ctx, mesh, s);
+    if (st != SPOLY_OK) return st;
+    const int64_t npair = int64_t(mesh->n_tris) * mesh->n_tris;
+    if (ctx->pairs_cap < npair) {
+        if (ctx->pairs) (void)hipFree(ctx->pairs);
+        ctx->pairs = nullptr;
+        ctx->pairs_cap = 0;
+        if (hipMalloc(&ctx->pairs, sizeof(int2) * size_t(npair)) != hipSuccess) return SPOLY_E_DEVICE;
+        ctx->pairs_cap = npair;
+    }
+    if (!ctx->pair_count && hipMalloc(&ctx->pair_count, sizeof(unsigned long long)) != hipSuccess)
+        return SPOLY_E_DEVICE;
+    spoly::CullTTArgs A;
+    A.tri_cone = ctx->tri_cone;
+    A.n_tris = mesh->n_tris;
+    A.x0x = x0s->x; A.x0y = x0s->y; A.x0z = x0s->z;
+    A.x3x = x3s->x; A.x3y = x3s->y; A.x3z = x3s->z;
+    A.n0 = x0s->n; A.n3 = x3s->n;
+    A.eta0 = float(eta[0]); A.eta1 = float(eta[1]); A.eta2 = float(eta[2]); A.margin = float(margin);
+    A.pairs = ctx->pairs; A.pair_cap = ctx->pairs_cap; A.pair_count = ctx->pair_count;
+    A.out_x0 = out_x0; A.out_x3 = out_x3; A.out_t1 = out_t1; A.out_t2 = out_t2;
+    A.cap = out_capacity; A.out_count = out_count;
+    for (int j3 = 0; j3 < x3s->n; ++j3) {
+        if (spoly::launch_zero_u64(ctx->pair_count, s) != hipSuccess) return SPOLY_E_DEVICE;
+        if (spoly::launch_tt_pairs(A, j3, s) != hipSuccess) return SPOLY_E_DEVICE;
+        unsigned long long np = 0;
+        if (hipMemcpyAsync(&np, ctx->pair_count, sizeof(np), hipMemcpyDeviceToHost, s) != hipSuccess) return SPOLY_E_DEVICE;
+        if (hipStreamSynchronize(s) != hipSuccess) return SPOLY_E_DEVICE;
+        if (np > (unsigned long long)ctx->pairs_cap) np = (unsigned long long)ctx->pairs_cap;
+        if (spoly::launch_tt_cull(A, j3, int64_t(np), s) != hipSuccess) return SPOLY_E_DEVICE;
+    }
+    return SPOLY_OK;
+}
+
+spoly_status spoly_solve_nbounce(spoly_ctx* ctx, const spoly_mesh* mesh, int32_t k, const spoly_event* chain,
+                                 const double* eta, const spoly_points* x0s, const spoly_points* x3s,
+                                 const int32_t* q_x0, const int32_t* q_x3, const int32_t* q_tris, int64_t n_queries,
+                                 spoly_precision prec, const spoly_params* params, const double* sqrt_table,
+                                 spoly_solution* out, int64_t out_capacity, unsigned long long* out_count,
+                                 unsigned long long* counters, int32_t* diag_q, void* stream)
+{
+    if (!ctx || !mesh_ok(mesh) || !pts_ok(x0s) || !pts_ok(x3s) || !params || !out_count || !chain || !eta)
+        return SPOLY_E_INVALID_ARG;
+    if (n_queries < 0 || out_capacity < 0 || (out_capacity > 0 && !out)) return SPOLY_E_INVALID_ARG;
+    if (n_queries > 0 && (!q_x0 || !q_x3 || !q_tris)) return SPOLY_E_INVALID_ARG;
+    if (k != 2) return SPOLY_E_UNSUPPORTED;
+    if (chain[0] != SPOLY_T || chain[1] != SPOLY_T) return SPOLY_E_UNSUPPORTED;
+    if (prec != SPOLY_FP64) return SPOLY_E_UNSUPPORTED;
+    if (!(eta[0] > 0.0) || !(eta[1] > 0.0) || !(eta[2] > 0.0)) return SPOLY_E_INVALID_ARG;
+    if (params->pieces < 1 || params->pieces > 127 || params->bisect_iters < 0 || params->polish_iters < 0 ||
+        !(params->tau > 0.0) || !(params->u_margin >= 0.0) || !(params->dedup >= 0.0))
+        return SPOLY_E_INVALID_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess) return SPOLY_E_DEVICE;
+    spoly::TTArgs A;
+    A.px = mesh->px; A.py = mesh->py; A.pz = mesh->pz;
+    A.nx = mesh->nx; A.ny = mesh->ny; A.nz = mesh->nz;
+    A.tri = mesh->tri;
+    A.x0x = x0s->x; A.x0y = x0s->y; A.x0z = x0s->z;
+    A.x3x = x3s->x; A.x3y = x3s->y; A.x3z = x3s->z;
+    A.q_x0 = q_x0; A.q_x3 = q_x3; A.q_tris = q_tris;
+    A.nq = n_queries;
+    A.eta0 = eta[0]; A.eta1 = eta[1]; A.eta2 = eta[2];
+    const double* tb = sqrt_table ? sqrt_table : nullptr;
+    for (int i = 0; i < 7; ++i) A.sqrt_bp[i] = tb ? tb[i] : kSqrtPieceEnds[i];
+    for (int i = 0; i < 24; ++i) A.sqrt_c[i] = tb ? tb[7 + i] : kSqrtCoef[i];
+    A.pieces = params->pieces; A.bisect_iters = params->bisect_iters; A.polish_iters = params->polish_iters;
+    A.tau = params->tau; A.u_margin = params->u_margin; A.dedup = params->dedup;
+    A.out = out; A.cap = out_capacity; A.out_count = out_count;
+    A.counters = counters; A.diag_q = diag_q;
+    return dev_err(spoly::launch_tt_solve(A, static_cast<hipStream_t>(stream)));
 }
 
 }  // extern "C"

@@ -37,14 +37,45 @@ __global__ void __launch_bounds__(256) k_tri_cones(const double* px, const doubl
     cone[2 * t + 1] = make_float4(float(an.x), float(an.y), float(an.z), float(th + 1e-6));
 }
 
-constexpr int kCullPts = 16;  // (x0, x2) pairs per thread
+constexpr int kCullPts = 64;  // (x0, x2) pairs per thread; one atomic per wave per 64 pairs
 
+__device__ __forceinline__ bool cone_keep(float4 c0, float4 c1, float px, float py, float pz, float qx, float qy,
+                                          float qz, float eta0, float eta1, float margin)
+{
+    float ax = px - c0.x, ay = py - c0.y, az = pz - c0.z;
+    float bx = qx - c0.x, by = qy - c0.y, bz = qz - c0.z;
+    float da = sqrtf(ax * ax + ay * ay + az * az), db = sqrtf(bx * bx + by * by + bz * bz);
+    const float rad = c0.w;
+    if (!(da > rad * 1.0001f) || !(db > rad * 1.0001f) || !(c1.w < 1.5707f)) return true;
+    float ia = 1.0f / da, ib = 1.0f / db;
+    ax *= ia; ay *= ia; az *= ia;
+    bx *= ib; by *= ib; bz *= ib;
+    float sa = rad * ia, sb = rad * ib;
+    float chord_a = sqrtf(fmaxf(0.0f, 2.0f - 2.0f * sqrtf(fmaxf(0.0f, 1.0f - sa * sa))));
+    float chord_b = sqrtf(fmaxf(0.0f, 2.0f - 2.0f * sqrtf(fmaxf(0.0f, 1.0f - sb * sb))));
+    float hx = eta0 * ax + eta1 * bx, hy = eta0 * ay + eta1 * by, hz = eta0 * az + eta1 * bz;
+    float L = sqrtf(hx * hx + hy * hy + hz * hz);
+    float delta = (eta0 * chord_a + eta1 * chord_b) * 1.0001f + 1e-6f;
+    if (!(delta < L)) return true;
+    float lim = c1.w + asinf(fminf(1.0f, delta / L)) + margin;
+    if (lim >= 1.5707f) return true;
+    float cphi = fabsf(c1.x * hx + c1.y * hy + c1.z * hz) / L;
+    return cphi >= cosf(lim) * (1.0f - 1e-6f);
+}
+
+// Grid: (pair block) x (triangle block of 256).  Each thread tests one
+// triangle against kCullPts consecutive (x0, x2) pairs, keeping the wave's
+// per-pair ballots in LDS; the wave then reserves its whole output range with
+// one atomic and writes the kept triples pair by pair (coalesced).
 __global__ void __launch_bounds__(256) k_cull_1bounce(CullArgs A)
 {
+    __shared__ unsigned long long s_bal[4][kCullPts];
     const int ntb = (A.n_tris + 255) / 256;
     const int t = int(blockIdx.x % ntb) * blockDim.x + threadIdx.x;
     const int64_t pblock = int64_t(blockIdx.x / ntb);
     const bool tri_ok = t < A.n_tris;
+    const int w = threadIdx.x / kWave;
+    const int lane = lane_id();
     float4 c0 = make_float4(0, 0, 0, 0), c1 = make_float4(0, 0, 0, 4.0f);
     if (tri_ok) {
         c0 = A.tri_cone[2 * t];
@@ -52,58 +83,39 @@ __global__ void __launch_bounds__(256) k_cull_1bounce(CullArgs A)
     }
     const int64_t n_pairs = int64_t(A.n0) * A.n2;
     const int64_t pair0 = pblock * kCullPts;
-    for (int k = 0; k < kCullPts; ++k) {
+    const int npairs = int(min<int64_t>(kCullPts, n_pairs - pair0));
+    int mine = 0;
+    for (int k = 0; k < npairs; ++k) {
         const int64_t pr = pair0 + k;
-        if (pr >= n_pairs) break;  // uniform across the block
         const int j0 = int(pr / A.n2), j2 = int(pr % A.n2);
-        bool keep = false;
-        if (tri_ok) {
-            float ax = float(A.x0x[j0]) - c0.x, ay = float(A.x0y[j0]) - c0.y, az = float(A.x0z[j0]) - c0.z;
-            float bx = float(A.x2x[j2]) - c0.x, by = float(A.x2y[j2]) - c0.y, bz = float(A.x2z[j2]) - c0.z;
-            float da = sqrtf(ax * ax + ay * ay + az * az), db = sqrtf(bx * bx + by * by + bz * bz);
-            const float rad = c0.w;
-            if (!(da > rad * 1.0001f) || !(db > rad * 1.0001f) || !(c1.w < 1.5707f)) {
-                keep = true;
-            } else {
-                float ia = 1.0f / da, ib = 1.0f / db;
-                ax *= ia; ay *= ia; az *= ia;
-                bx *= ib; by *= ib; bz *= ib;
-                float sa = rad * ia, sb = rad * ib;
-                float chord_a = sqrtf(fmaxf(0.0f, 2.0f - 2.0f * sqrtf(fmaxf(0.0f, 1.0f - sa * sa))));
-                float chord_b = sqrtf(fmaxf(0.0f, 2.0f - 2.0f * sqrtf(fmaxf(0.0f, 1.0f - sb * sb))));
-                float hx = A.eta0 * ax + A.eta1 * bx, hy = A.eta0 * ay + A.eta1 * by, hz = A.eta0 * az + A.eta1 * bz;
-                float L = sqrtf(hx * hx + hy * hy + hz * hz);
-                float delta = (A.eta0 * chord_a + A.eta1 * chord_b) * 1.0001f + 1e-6f;
-                if (!(delta < L)) {
-                    keep = true;
-                } else {
-                    float lim = c1.w + asinf(fminf(1.0f, delta / L)) + A.margin;
-                    if (lim >= 1.5707f) {
-                        keep = true;
-                    } else {
-                        float cphi = fabsf(c1.x * hx + c1.y * hy + c1.z * hz) / L;
-                        keep = cphi >= cosf(lim) * (1.0f - 1e-6f);
-                    }
-                }
-            }
-        }
-        // wave-ballot compaction of the kept triples
+        bool keep = tri_ok && cone_keep(c0, c1, float(A.x0x[j0]), float(A.x0y[j0]), float(A.x0z[j0]), float(A.x2x[j2]),
+                                        float(A.x2y[j2]), float(A.x2z[j2]), A.eta0, A.eta1, A.margin);
         const unsigned long long bal = __ballot(keep);
-        const int total = __popcll(bal);
-        if (total == 0) continue;
-        const int lane = lane_id();
-        const int before = __popcll(bal & ((1ull << lane) - 1ull));
-        unsigned long long base = 0;
-        if (lane == 0) base = atomicAdd(A.out_count, (unsigned long long)total);
-        base = __shfl(base, 0, kWave);
-        if (keep) {
-            unsigned long long idx = base + before;
+        if (lane == 0) s_bal[w][k] = bal;
+        mine += keep ? 1 : 0;
+    }
+    const int incl = wave_incl_scan(mine);
+    const int total = __shfl(incl, kWave - 1, kWave);
+    if (total == 0) return;
+    unsigned long long base = 0;
+    if (lane == kWave - 1) base = atomicAdd(A.out_count, (unsigned long long)total);
+    base = __shfl(base, kWave - 1, kWave);
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+    unsigned long long off = base;
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    for (int k = 0; k < npairs; ++k) {
+        const unsigned long long bal = s_bal[w][k];
+        if ((bal >> lane) & 1ull) {
+            const unsigned long long idx = off + (unsigned long long)__popcll(bal & lt);
             if (idx < (unsigned long long)A.cap) {
-                A.out_x0[idx] = j0;
-                A.out_x2[idx] = j2;
+                const int64_t pr = pair0 + k;
+                A.out_x0[idx] = int(pr / A.n2);
+                A.out_x2[idx] = int(pr % A.n2);
                 A.out_tri[idx] = t;
             }
         }
+        off += (unsigned long long)__popcll(bal);
     }
 }
 

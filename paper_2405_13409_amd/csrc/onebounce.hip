@@ -299,9 +299,24 @@ __device__ __forceinline__ void solve_instance(const Geo& g, const OneBounceArgs
     using Y = Sys<R, EV, F>;
     P2<R, Y::TA> a;
     P2<R, Y::TB> b;
-    build_ab<R, EV, F>(g, A.eta0, A.eta1, a, b);
-    normalise(a);
-    normalise(b);
+    if constexpr (EV == SPOLY_T && sizeof(R) == 4) {
+        // The square form is a difference of two nearly equal squares over a
+        // small triangle; its coefficients are built in FP64 and rounded to FP32
+        // only after normalisation.
+        P2<double, Y::TA> a64;
+        P2<double, Y::TB> b64;
+        build_ab<double, EV, F>(g, A.eta0, A.eta1, a64, b64);
+        normalise(a64);
+        normalise(b64);
+#pragma unroll
+        for (int k = 0; k < tri_size(Y::TA); ++k) a.c[k] = R(a64.c[k]);
+#pragma unroll
+        for (int k = 0; k < tri_size(Y::TB); ++k) b.c[k] = R(b64.c[k]);
+    } else {
+        build_ab<R, EV, F>(g, A.eta0, A.eta1, a, b);
+        normalise(a);
+        normalise(b);
+    }
     R r[Y::DR + 1];
     eliminate<R, EV, F>(a.c, b.c, r);
     R rmax = R(0);

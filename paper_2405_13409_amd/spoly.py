@@ -25,7 +25,7 @@ SOLUTION_DTYPE = np.dtype([("query", "<i4"), ("tri", "<i4", (2,)), ("flags", "<u
 assert SOLUTION_DTYPE.itemsize == 56
 
 EXPORTED = ("spoly_ctx_create", "spoly_ctx_destroy", "spoly_default_params", "spoly_status_str",
-            "spoly_cull_1bounce", "spoly_solve_1bounce")
+            "spoly_cull_1bounce", "spoly_solve_1bounce", "spoly_cull_2bounce", "spoly_solve_nbounce")
 
 
 class SpolyError(RuntimeError):
@@ -74,6 +74,13 @@ def load_library(path: str = LIB_PATH):
     L.spoly_solve_1bounce.argtypes = [P, ctypes.POINTER(Mesh), ctypes.POINTER(Points), ctypes.POINTER(Points), P, P, P,
                                       I64, ctypes.c_int, D, D, ctypes.c_int, ctypes.POINTER(Params), P, I64, P, P, P, P]
     L.spoly_solve_1bounce.restype = ctypes.c_int
+    L.spoly_cull_2bounce.argtypes = [P, ctypes.POINTER(Mesh), ctypes.POINTER(Points), ctypes.POINTER(Points), P, D,
+                                     P, P, P, P, I64, P, P]
+    L.spoly_cull_2bounce.restype = ctypes.c_int
+    L.spoly_solve_nbounce.argtypes = [P, ctypes.POINTER(Mesh), I32, P, P, ctypes.POINTER(Points),
+                                      ctypes.POINTER(Points), P, P, P, I64, ctypes.c_int, ctypes.POINTER(Params), P, P,
+                                      I64, P, P, P, P]
+    L.spoly_solve_nbounce.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -196,6 +203,68 @@ class Context:
             if out is not None:
                 raise SpolyError(f"output capacity {capn} < {n} solutions")
             cap = n
+
+
+def _host_doubles(vals):
+    arr = (ctypes.c_double * len(vals))(*[float(v) for v in vals])
+    return arr
+
+
+def _cull_2bounce(self, mesh: DeviceMesh, x0s: DevicePoints, x3s: DevicePoints, eta=(1.0, 1.5, 1.0),
+                  margin=1e-3, capacity: int | None = None):
+    """Returns int32 device tensors (q_x0, q_x3, q_tris [n,2]) of the kept tuples."""
+    L = load_library()
+    cap = capacity if capacity is not None else 1 << 22
+    e = _host_doubles(eta)
+    while True:
+        q0 = torch.empty(cap, dtype=torch.int32, device="cuda")
+        q3 = torch.empty(cap, dtype=torch.int32, device="cuda")
+        t1 = torch.empty(cap, dtype=torch.int32, device="cuda")
+        t2 = torch.empty(cap, dtype=torch.int32, device="cuda")
+        cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+        _check(L.spoly_cull_2bounce(self.h, ctypes.byref(mesh.c), ctypes.byref(x0s.c), ctypes.byref(x3s.c), e,
+                                    margin, _ptr(q0), _ptr(q3), _ptr(t1), _ptr(t2), cap, _ptr(cnt), _stream()),
+               "spoly_cull_2bounce")
+        n = int(cnt.item())
+        if n <= cap:
+            return q0[:n], q3[:n], torch.stack([t1[:n], t2[:n]], 1).contiguous()
+        cap = n
+
+
+def _solve_2bounce(self, mesh: DeviceMesh, x0s: DevicePoints, x3s: DevicePoints, q_x0: torch.Tensor,
+                   q_x3: torch.Tensor, q_tris: torch.Tensor, eta=(1.0, 1.5, 1.0), params: Params | None = None,
+                   sqrt_table=None, capacity: int | None = None, counters: torch.Tensor | None = None,
+                   diag: torch.Tensor | None = None, sync: bool = True, out=None, out_count=None):
+    """TT chain x0 -> T1 -> T2 -> x3 (refraction at both vertices)."""
+    L = load_library()
+    nq = int(q_x0.numel())
+    prm = params or default_params()
+    chain = (ctypes.c_int * 2)(SPOLY_T, SPOLY_T)
+    e = _host_doubles(eta)
+    tb = _host_doubles(sqrt_table) if sqrt_table is not None else None
+    cap = capacity if capacity is not None else max(1024, nq // 8)
+    while True:
+        buf = out if out is not None else torch.empty(cap * SOLUTION_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+        cnt = out_count if out_count is not None else torch.zeros(1, dtype=torch.int64, device="cuda")
+        if out_count is not None:
+            cnt.zero_()
+        _check(L.spoly_solve_nbounce(self.h, ctypes.byref(mesh.c), 2, chain, e, ctypes.byref(x0s.c),
+                                     ctypes.byref(x3s.c), _ptr(q_x0), _ptr(q_x3), _ptr(q_tris), nq, SPOLY_FP64,
+                                     ctypes.byref(prm), tb, _ptr(buf), buf.numel() // SOLUTION_DTYPE.itemsize,
+                                     _ptr(cnt), _ptr(counters), _ptr(diag), _stream()), "spoly_solve_nbounce")
+        if not sync:
+            return buf, cnt
+        n = int(cnt.item())
+        capn = buf.numel() // SOLUTION_DTYPE.itemsize
+        if n <= capn:
+            return buf[: n * SOLUTION_DTYPE.itemsize].cpu().numpy().view(SOLUTION_DTYPE)
+        if out is not None:
+            raise SpolyError(f"output capacity {capn} < {n} solutions")
+        cap = n
+
+
+Context.cull_2bounce = _cull_2bounce
+Context.solve_2bounce = _solve_2bounce
 
 
 def sort_solutions(s: np.ndarray) -> np.ndarray:
