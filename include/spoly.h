@@ -209,6 +209,47 @@ spoly_status spoly_solve_nbounce(spoly_ctx *ctx, const spoly_mesh *mesh, int32_t
                                  spoly_solution *out, int64_t out_capacity, unsigned long long *out_count,
                                  unsigned long long *counters, int32_t *diag_q, void *stream);
 
+/*
+ * S8 -- learned pruner of two-vertex tuples (callers who want to skip tuples
+ * that cannot hold a path before spoly_solve_nbounce).  An MLP with 42 inputs
+ * (x0/2, x3/2, the positions of T1 and T2 divided by 2, the vertex normals of
+ * T1 and T2), three hidden layers of 128 ReLU units and a sigmoid output.
+ * params: device float [SPOLY_PRUNER_NPARAMS]: W1 [42 x 128] (row = input),
+ * b1 [128], W2 [128 x 128], b2 [128], W3 [128 x 128], b3 [128], W4 [128], b4 [1].
+ * Dense layers run on the matrix cores with bf16 operands and fp32
+ * accumulation; master parameters, gradients and optimizer state are fp32.
+ * Tuples are given as for spoly_solve_nbounce (q_x0, q_x3, q_tris[2q..2q+1]).
+ */
+#define SPOLY_PRUNER_NPARAMS 38657
+
+/* Scores in [0,1] (scores [n], optional) and the indices q of the tuples with
+ * score >= threshold (keep_idx [keep_capacity], order unspecified);
+ * *keep_count (device uint64, zeroed by the caller) receives the total kept. */
+spoly_status spoly_prune_score(spoly_ctx *ctx, const spoly_mesh *mesh, const spoly_points *x0s,
+                               const spoly_points *x3s, const int32_t *q_x0, const int32_t *q_x3,
+                               const int32_t *q_tris, int64_t n, const float *params, float threshold,
+                               float *scores, int32_t *keep_idx, int64_t keep_capacity,
+                               unsigned long long *keep_count, void *stream);
+
+/* Forward and backward pass of one batch under the class-weighted binary cross
+ * entropy  mean_q [ -w y_q log p_q - (1 - y_q) log(1 - p_q) ],  w = pos_weight
+ * for positives.  labels [n] in {0,1}; grads [SPOLY_PRUNER_NPARAMS] (written);
+ * *loss (device float) accumulates the batch loss.  n <= 65536. */
+spoly_status spoly_pruner_fwd_bwd(spoly_ctx *ctx, const spoly_mesh *mesh, const spoly_points *x0s,
+                                  const spoly_points *x3s, const int32_t *q_x0, const int32_t *q_x3,
+                                  const int32_t *q_tris, int64_t n, const float *labels, float pos_weight,
+                                  const float *params, float *grads, float *loss, void *stream);
+
+/* Adam step (step >= 1, bias-corrected) on params with grads and moment
+ * buffers adam_m, adam_v [SPOLY_PRUNER_NPARAMS] (zero-initialised by the caller). */
+spoly_status spoly_pruner_step(spoly_ctx *ctx, float *params, const float *grads, float *adam_m, float *adam_v,
+                               int64_t step, float lr, float beta1, float beta2, float eps, void *stream);
+
+/* Features of n tuples as fp32 [n x 48] (42 used, 6 zero), the network input. */
+spoly_status spoly_pruner_features(spoly_ctx *ctx, const spoly_mesh *mesh, const spoly_points *x0s,
+                                   const spoly_points *x3s, const int32_t *q_x0, const int32_t *q_x3,
+                                   const int32_t *q_tris, int64_t n, float *features, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

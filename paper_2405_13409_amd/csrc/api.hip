@@ -9,6 +9,7 @@
 #include "onebounce.hpp"
 #include "twobounce.hpp"
 #include "sqrt_table.inc"
+#include "pruner.hpp"
 
 struct spoly_ctx {
     int device;
@@ -17,6 +18,8 @@ struct spoly_ctx {
     int2* pairs;           // two-vertex cull: (T1, T2) pairs of one light
     int64_t pairs_cap;
     unsigned long long* pair_count;
+    spoly::PrunerWork pw;  // pruner training activations
+    void* pw_block;
 };
 
 namespace {
@@ -78,6 +81,7 @@ void spoly_ctx_destroy(spoly_ctx* ctx)
     if (ctx->tri_cone) (void)hipFree(ctx->tri_cone);
     if (ctx->pairs) (void)hipFree(ctx->pairs);
     if (ctx->pair_count) (void)hipFree(ctx->pair_count);
+    if (ctx->pw_block) (void)hipFree(ctx->pw_block);
     std::free(ctx);
 }
 
@@ -237,6 +241,109 @@ spoly_status spoly_solve_nbounce(spoly_ctx* ctx, const spoly_mesh* mesh, int32_t
     A.out = out; A.cap = out_capacity; A.out_count = out_count;
     A.counters = counters; A.diag_q = diag_q;
     return dev_err(spoly::launch_tt_solve(A, static_cast<hipStream_t>(stream)));
+}
+
+}  // extern "C"
+
+namespace {
+
+bool fill_io(spoly::PrunerIO& io, const spoly_mesh* mesh, const spoly_points* x0s, const spoly_points* x3s,
+             const int32_t* q_x0, const int32_t* q_x3, const int32_t* q_tris, int64_t n)
+{
+    if (!mesh_ok(mesh) || !pts_ok(x0s) || !pts_ok(x3s) || n < 0) return false;
+    if (n > 0 && (!q_x0 || !q_x3 || !q_tris)) return false;
+    io.px = mesh->px; io.py = mesh->py; io.pz = mesh->pz;
+    io.nx = mesh->nx; io.ny = mesh->ny; io.nz = mesh->nz;
+    io.tri = mesh->tri;
+    io.x0x = x0s->x; io.x0y = x0s->y; io.x0z = x0s->z;
+    io.x3x = x3s->x; io.x3y = x3s->y; io.x3z = x3s->z;
+    io.q_x0 = q_x0; io.q_x3 = q_x3; io.q_tris = q_tris;
+    io.n = n;
+    return true;
+}
+
+spoly_status ensure_pruner_work(spoly_ctx* ctx, int64_t n)
+{
+    if (ctx->pw_block && ctx->pw.cap >= n) return SPOLY_OK;
+    if (ctx->pw_block) (void)hipFree(ctx->pw_block);
+    ctx->pw_block = nullptr;
+    const int64_t cap = n < 1024 ? 1024 : n;
+    const size_t bf = 2, f4 = 4;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off += (bytes + 255) & ~size_t(255); return o; };
+    size_t oX = take(cap * spoly::kFeat * bf), oPb = take(size_t(spoly::kNParams) * bf);
+    size_t oH1 = take(cap * spoly::kHid * bf), oH2 = take(cap * spoly::kHid * bf), oH3 = take(cap * spoly::kHid * bf);
+    size_t odZ4 = take(cap * 16 * bf), odZ = take(cap * spoly::kHid * bf);
+    size_t oZ1 = take(cap * spoly::kHid * f4), oZ2 = take(cap * spoly::kHid * f4), oZ3 = take(cap * spoly::kHid * f4);
+    size_t oZ4 = take(cap * 16 * f4), odH = take(cap * spoly::kHid * f4);
+    if (hipMalloc(&ctx->pw_block, off) != hipSuccess) { ctx->pw_block = nullptr; return SPOLY_E_DEVICE; }
+    char* b = static_cast<char*>(ctx->pw_block);
+    spoly::PrunerWork& W = ctx->pw;
+    W.cap = cap;
+    W.X = (unsigned short*)(b + oX); W.Pb = (unsigned short*)(b + oPb);
+    W.H1 = (unsigned short*)(b + oH1); W.H2 = (unsigned short*)(b + oH2); W.H3 = (unsigned short*)(b + oH3);
+    W.dZ4 = (unsigned short*)(b + odZ4); W.dZ = (unsigned short*)(b + odZ);
+    W.Z1 = (float*)(b + oZ1); W.Z2 = (float*)(b + oZ2); W.Z3 = (float*)(b + oZ3); W.Z4 = (float*)(b + oZ4);
+    W.dH = (float*)(b + odH);
+    return SPOLY_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+spoly_status spoly_prune_score(spoly_ctx* ctx, const spoly_mesh* mesh, const spoly_points* x0s,
+                               const spoly_points* x3s, const int32_t* q_x0, const int32_t* q_x3,
+                               const int32_t* q_tris, int64_t n, const float* params, float threshold, float* scores,
+                               int32_t* keep_idx, int64_t keep_capacity, unsigned long long* keep_count, void* stream)
+{
+    spoly::PrunerIO io;
+    if (!ctx || !params || !keep_count || keep_capacity < 0 || (keep_capacity > 0 && !keep_idx)) return SPOLY_E_INVALID_ARG;
+    if (!fill_io(io, mesh, x0s, x3s, q_x0, q_x3, q_tris, n)) return SPOLY_E_INVALID_ARG;
+    if (!(threshold >= 0.0f) || !(threshold <= 1.0f)) return SPOLY_E_INVALID_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess) return SPOLY_E_DEVICE;
+    return dev_err(spoly::launch_prune_score(io, params, threshold, scores, keep_idx, keep_capacity, keep_count,
+                                             static_cast<hipStream_t>(stream)));
+}
+
+spoly_status spoly_pruner_fwd_bwd(spoly_ctx* ctx, const spoly_mesh* mesh, const spoly_points* x0s,
+                                  const spoly_points* x3s, const int32_t* q_x0, const int32_t* q_x3,
+                                  const int32_t* q_tris, int64_t n, const float* labels, float pos_weight,
+                                  const float* params, float* grads, float* loss, void* stream)
+{
+    spoly::PrunerIO io;
+    if (!ctx || !labels || !params || !grads || !loss || n <= 0 || n > 65536) return SPOLY_E_INVALID_ARG;
+    if (!fill_io(io, mesh, x0s, x3s, q_x0, q_x3, q_tris, n)) return SPOLY_E_INVALID_ARG;
+    if (!(pos_weight > 0.0f)) return SPOLY_E_INVALID_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess) return SPOLY_E_DEVICE;
+    spoly_status st = ensure_pruner_work(ctx, n);
+    if (st != SPOLY_OK) return st;
+    return dev_err(spoly::pruner_fwd_bwd(io, labels, pos_weight, params, grads, loss, ctx->pw,
+                                         static_cast<hipStream_t>(stream)));
+}
+
+spoly_status spoly_pruner_step(spoly_ctx* ctx, float* params, const float* grads, float* adam_m, float* adam_v,
+                               int64_t step, float lr, float beta1, float beta2, float eps, void* stream)
+{
+    if (!ctx || !params || !grads || !adam_m || !adam_v || step < 1) return SPOLY_E_INVALID_ARG;
+    if (!(lr > 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+        return SPOLY_E_INVALID_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess) return SPOLY_E_DEVICE;
+    return dev_err(spoly::pruner_adam(params, grads, adam_m, adam_v, step, lr, beta1, beta2, eps,
+                                      static_cast<hipStream_t>(stream)));
+}
+
+spoly_status spoly_pruner_features(spoly_ctx* ctx, const spoly_mesh* mesh, const spoly_points* x0s,
+                                   const spoly_points* x3s, const int32_t* q_x0, const int32_t* q_x3,
+                                   const int32_t* q_tris, int64_t n, float* features, void* stream)
+{
+    spoly::PrunerIO io;
+    if (!ctx || !features) return SPOLY_E_INVALID_ARG;
+    if (!fill_io(io, mesh, x0s, x3s, q_x0, q_x3, q_tris, n)) return SPOLY_E_INVALID_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess) return SPOLY_E_DEVICE;
+    spoly_status st = ensure_pruner_work(ctx, n);
+    if (st != SPOLY_OK) return st;
+    return dev_err(spoly::launch_gather(io, ctx->pw.X, features, static_cast<hipStream_t>(stream)));
 }
 
 }  // extern "C"

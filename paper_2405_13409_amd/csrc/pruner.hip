@@ -1,0 +1,464 @@
+// S8: learned pruner of two-vertex tuples.  An MLP 42 -> 128 -> 128 -> 128 -> 1
+// (ReLU, sigmoid) scores each (x0, T1, T2, x3) tuple from the separators and
+// the positions / normals of both triangles; tuples scoring below a
+// calibrated threshold are not sent to the solver.  Dense layers run on the
+// matrix cores: bf16 operands, fp32 accumulation (v_mfma_f32_16x16x16_bf16).
+//   training : k_gather -> 4 x (GEMM, bias/ReLU) -> loss gradient -> backward
+//              GEMMs (split-K for weight gradients) -> Adam
+//   inference: one fused kernel, weights staged in LDS, 16 tuples per wave tile.
+#include <hip/hip_bf16.h>
+
+#include "spoly_dev.hpp"
+#include "pruner.hpp"
+
+namespace spoly {
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned short f2bf(float f)
+{
+    // round to nearest even
+    unsigned int u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)(u >> 16);  // inf / nan
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
+
+// ------------------------------------------------------------------ features
+// 42 features: x0/2, x3/2, the three positions of T1 and of T2 divided by 2,
+// the three vertex normals of T1 and of T2 (as given).  Padded to kFeat = 48.
+__global__ void __launch_bounds__(256) k_gather(PrunerIO io, unsigned short* X, float* Xf)
+{
+    const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (q >= io.n) return;
+    float f[kFeat];
+#pragma unroll
+    for (int k = 0; k < kFeat; ++k) f[k] = 0.0f;
+    const int j0 = io.q_x0[q], j3 = io.q_x3[q];
+    const int t1 = io.q_tris[2 * q], t2 = io.q_tris[2 * q + 1];
+    f[0] = float(io.x0x[j0] * 0.5); f[1] = float(io.x0y[j0] * 0.5); f[2] = float(io.x0z[j0] * 0.5);
+    f[3] = float(io.x3x[j3] * 0.5); f[4] = float(io.x3y[j3] * 0.5); f[5] = float(io.x3z[j3] * 0.5);
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+        const int a = io.tri[3 * t1 + v], b = io.tri[3 * t2 + v];
+        f[6 + 3 * v + 0] = float(io.px[a] * 0.5); f[6 + 3 * v + 1] = float(io.py[a] * 0.5); f[6 + 3 * v + 2] = float(io.pz[a] * 0.5);
+        f[15 + 3 * v + 0] = float(io.px[b] * 0.5); f[15 + 3 * v + 1] = float(io.py[b] * 0.5); f[15 + 3 * v + 2] = float(io.pz[b] * 0.5);
+        f[24 + 3 * v + 0] = float(io.nx[a]); f[24 + 3 * v + 1] = float(io.ny[a]); f[24 + 3 * v + 2] = float(io.nz[a]);
+        f[33 + 3 * v + 0] = float(io.nx[b]); f[33 + 3 * v + 1] = float(io.ny[b]); f[33 + 3 * v + 2] = float(io.nz[b]);
+    }
+#pragma unroll
+    for (int k = 0; k < kFeat; ++k) {
+        X[q * kFeat + k] = f2bf(f[k]);
+        if (Xf) Xf[q * kFeat + k] = f[k];
+    }
+}
+
+// ------------------------------------------------------------------ generic bf16 GEMM on MFMA
+// C(m,n) (+)= sum_k A(m,k) B(k,n), A(m,k) = A[m*sam + k*sak], B(k,n) = B[k*sbk + n*sbn],
+// fp32 C row-major with leading dimension ldc.  64x64 tile per workgroup
+// (2x2 waves of 32x32, each 2x2 MFMA 16x16 tiles), K in steps of 16; blockIdx.z
+// splits K, partial sums are added atomically (C zeroed by the caller).
+// Operand fragments: lane l holds rows/cols (l & 15) and k = 4 (l >> 4) + i.
+__global__ void __launch_bounds__(256) k_gemm(GemmArgs G)
+{
+    const int lane = lane_id();
+    const int w = threadIdx.x / kWave;
+    const int m0 = blockIdx.y * 64 + (w >> 1) * 32;
+    const int n0 = blockIdx.x * 64 + (w & 1) * 32;
+    const int kchunk = (G.K + gridDim.z - 1) / gridDim.z;
+    const int kbeg = blockIdx.z * kchunk;
+    const int kend = min(G.K, kbeg + kchunk);
+    v4f acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+    const int r = lane & 15, kq = (lane >> 4) * 4;
+    for (int k0 = kbeg; k0 < kend; k0 += 16) {
+        v4s af[2], bfr[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const int m = m0 + 16 * t + r;
+            const int n = n0 + 16 * t + r;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int k = k0 + kq + i;
+                const bool kin = k < kend;
+                af[t][i] = (kin && m < G.M) ? (short)G.A[int64_t(m) * G.sam + int64_t(k) * G.sak] : (short)0;
+                bfr[t][i] = (kin && n < G.N) ? (short)G.B[int64_t(k) * G.sbk + int64_t(n) * G.sbn] : (short)0;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[i], bfr[j], acc[i][j], 0, 0, 0);
+    }
+    // D fragment: lane holds column (lane & 15), rows 4 (lane >> 4) + i
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int m = m0 + 16 * i + kq + e;
+                const int n = n0 + 16 * j + r;
+                if (m < G.M && n < G.N) {
+                    float* c = G.C + int64_t(m) * G.ldc + n;
+                    if (gridDim.z > 1) atomicAdd(c, G.alpha * acc[i][j][e]);
+                    else *c = G.alpha * acc[i][j][e] + (G.accumulate ? *c : 0.0f);
+                }
+            }
+}
+
+hipError_t launch_gemm(const GemmArgs& G, int split_k, hipStream_t stream)
+{
+    if (G.M <= 0 || G.N <= 0 || G.K <= 0) return hipSuccess;
+    dim3 grid((G.N + 63) / 64, (G.M + 63) / 64, split_k < 1 ? 1 : split_k);
+    hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, stream, G);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ elementwise pieces of training
+// Z (fp32, [n x ncol]) += bias; H = relu(Z) in bf16 (row stride ncol)
+__global__ void k_bias_relu(float* Z, const float* bias, unsigned short* H, int64_t n, int ncol, int relu)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n * ncol) return;
+    const int c = int(i % ncol);
+    float z = Z[i] + bias[c];
+    Z[i] = z;
+    if (H) H[i] = f2bf(relu ? fmaxf(z, 0.0f) : z);
+}
+
+// logits z = Z4[:, 0]; weighted BCE; dZ4 (bf16, [n x 16], col 0) = d loss / d z
+__global__ void k_loss(const float* Z4, int ld, const float* b4, const float* labels, int64_t n, float pos_w,
+                       float inv_norm, unsigned short* dZ4, float* dz_f32, float* loss)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    float l = 0.0f;
+    if (i < n) {
+        const float z = Z4[i * ld] + b4[0];
+        const float y = labels[i];
+        const float p = 1.0f / (1.0f + expf(-z));
+        const float w = y > 0.5f ? pos_w : 1.0f;
+        // -[w y log p + (1-y) log(1-p)] with log p = -softplus(-z), log(1-p) = -softplus(z)
+        const float sp_neg = fmaxf(-z, 0.0f) + log1pf(expf(-fabsf(z)));
+        const float sp_pos = fmaxf(z, 0.0f) + log1pf(expf(-fabsf(z)));
+        l = (w * y * sp_neg + (1.0f - y) * sp_pos) * inv_norm;
+        const float g = (w * y * (p - 1.0f) + (1.0f - y) * p) * inv_norm;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) dZ4[i * 16 + c] = c == 0 ? f2bf(g) : (unsigned short)0;
+        if (dz_f32) dz_f32[i] = g;
+    }
+    float tot = l;
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) tot += __shfl_xor(tot, d, kWave);
+    if (lane_id() == 0 && tot != 0.0f) atomicAdd(loss, tot);
+}
+
+// dZ = dH * (Z > 0) -> bf16
+__global__ void k_relu_bwd(const float* dH, const float* Z, unsigned short* dZ, int64_t cnt)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= cnt) return;
+    dZ[i] = f2bf(Z[i] > 0.0f ? dH[i] : 0.0f);
+}
+
+// column sums of a bf16 matrix [n x ncol] (row stride ld) into db (fp32, accumulated)
+__global__ void k_colsum(const unsigned short* D, int64_t n, int ncol, int ld, float* db)
+{
+    const int c = blockIdx.x;
+    float s = 0.0f;
+    for (int64_t r = threadIdx.x; r < n; r += blockDim.x) s += bf2f(D[r * ld + c]);
+    __shared__ float red[256];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+        if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) db[c] += red[0];
+}
+
+// fp32 master parameters -> bf16 operand copies (weights stored [in x out] row-major)
+__global__ void k_to_bf16(const float* p, unsigned short* q, int64_t n)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) q[i] = f2bf(p[i]);
+}
+
+__global__ void k_fill(float* p, int64_t n, float v)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
+                       float eps, float c1, float c2)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// ------------------------------------------------------------------ fused inference
+// Weights in LDS, transposed to [out][in] so that each lane's four consecutive
+// k of a B fragment are one 8-byte read.  A wave scores 16 tuples per tile:
+// activations go through a 16 x 128 bf16 LDS buffer between layers (the D
+// fragment layout of one layer is not the A fragment layout of the next).
+constexpr int kW1 = kHid * kFeat, kW2 = kHid * kHid, kW4 = 16 * kHid;
+constexpr int kPruneLds = (kW1 + 2 * kW2 + kW4) * 2 + 4 * 16 * kHid * 2;
+
+__device__ __forceinline__ v4s lds4(const unsigned short* p)
+{
+    const uint2 u = *reinterpret_cast<const uint2*>(p);
+    v4s r;
+    r[0] = (short)(u.x & 0xffffu); r[1] = (short)(u.x >> 16);
+    r[2] = (short)(u.y & 0xffffu); r[3] = (short)(u.y >> 16);
+    return r;
+}
+
+template <int KIN>
+__device__ __forceinline__ void layer16(const unsigned short* act /*[16][KIN] bf16*/, const unsigned short* wt /*[out][KIN]*/,
+                                        int nout_tiles, v4f (&acc)[8])
+{
+    const int lane = lane_id(), r = lane & 15, kq = (lane >> 4) * 4;
+#pragma unroll
+    for (int nt = 0; nt < 8; ++nt) acc[nt] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k0 = 0; k0 < KIN; k0 += 16) {
+        const v4s a = lds4(act + r * KIN + k0 + kq);
+#pragma unroll
+        for (int nt = 0; nt < 8; ++nt)
+            if (nt < nout_tiles) {
+                const v4s b = lds4(wt + (nt * 16 + r) * KIN + k0 + kq);
+                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[nt], 0, 0, 0);
+            }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_prune_score(PrunerIO io, const float* params, float threshold,
+                                                     float* scores, int32_t* keep_idx, int64_t cap,
+                                                     unsigned long long* keep_count)
+{
+    extern __shared__ unsigned short sm[];
+    unsigned short* W1t = sm;              // [128][48]
+    unsigned short* W2t = W1t + kW1;       // [128][128]
+    unsigned short* W3t = W2t + kW2;
+    unsigned short* W4t = W3t + kW2;       // [16][128], row 0 real
+    unsigned short* act = W4t + kW4;       // 4 waves x [16][128]
+    const PrunerLayout L;
+    for (int i = threadIdx.x; i < kW1; i += blockDim.x) {
+        const int o = i / kFeat, k = i % kFeat;
+        W1t[i] = k < kIn ? f2bf(params[L.w1 + k * kHid + o]) : (unsigned short)0;
+    }
+    for (int i = threadIdx.x; i < kW2; i += blockDim.x) {
+        const int o = i / kHid, k = i % kHid;
+        W2t[i] = f2bf(params[L.w2 + k * kHid + o]);
+        W3t[i] = f2bf(params[L.w3 + k * kHid + o]);
+    }
+    for (int i = threadIdx.x; i < kW4; i += blockDim.x) {
+        const int o = i / kHid, k = i % kHid;
+        W4t[i] = o == 0 ? f2bf(params[L.w4 + k]) : (unsigned short)0;
+    }
+    __syncthreads();
+    const int w = threadIdx.x / kWave, lane = lane_id();
+    const int r = lane & 15, kq = (lane >> 4) * 4;
+    unsigned short* my = act + w * 16 * kHid;
+    const int64_t ntile = (io.n + 15) / 16;
+    for (int64_t tile = int64_t(blockIdx.x) * 4 + w; tile < ntile; tile += int64_t(gridDim.x) * 4) {
+        const int64_t q0 = tile * 16;
+        // gather features of 16 tuples: lane handles tuple r, features kq.. in chunks
+        {
+            const int64_t q = q0 + r;
+            const bool ok = q < io.n;
+            // each of the 4 lane groups fills 12 of the 48 features
+            float f[12];
+#pragma unroll
+            for (int k = 0; k < 12; ++k) f[k] = 0.0f;
+            if (ok) {
+                const int j0 = io.q_x0[q], j3 = io.q_x3[q];
+                const int t1 = io.q_tris[2 * q], t2 = io.q_tris[2 * q + 1];
+#pragma unroll
+                for (int k = 0; k < 12; ++k) {
+                    const int fi = (lane >> 4) * 12 + k;
+                    float val = 0.0f;
+                    if (fi < 3) val = float((fi == 0 ? io.x0x[j0] : fi == 1 ? io.x0y[j0] : io.x0z[j0]) * 0.5);
+                    else if (fi < 6) val = float((fi == 3 ? io.x3x[j3] : fi == 4 ? io.x3y[j3] : io.x3z[j3]) * 0.5);
+                    else if (fi < 42) {
+                        const int g = (fi - 6) / 9, rem = (fi - 6) % 9, v = rem / 3, c = rem % 3;
+                        const int tt = (g == 0 || g == 2) ? t1 : t2;
+                        const int vid = io.tri[3 * tt + v];
+                        if (g < 2) val = float((c == 0 ? io.px[vid] : c == 1 ? io.py[vid] : io.pz[vid]) * 0.5);
+                        else val = float(c == 0 ? io.nx[vid] : c == 1 ? io.ny[vid] : io.nz[vid]);
+                    }
+                    f[k] = val;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 12; ++k) my[r * kFeat + (lane >> 4) * 12 + k] = f2bf(f[k]);
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        __builtin_amdgcn_wave_barrier();
+        v4f acc[8];
+        // layer 1
+        layer16<kFeat>(my, W1t, 8, acc);
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int nt = 0; nt < 8; ++nt)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int col = nt * 16 + r, row = kq + e;
+                my[row * kHid + col] = f2bf(fmaxf(acc[nt][e] + params[L.b1 + col], 0.0f));
+            }
+        __builtin_amdgcn_s_waitcnt(0);
+        __builtin_amdgcn_wave_barrier();
+        layer16<kHid>(my, W2t, 8, acc);
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int nt = 0; nt < 8; ++nt)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int col = nt * 16 + r, row = kq + e;
+                my[row * kHid + col] = f2bf(fmaxf(acc[nt][e] + params[L.b2 + col], 0.0f));
+            }
+        __builtin_amdgcn_s_waitcnt(0);
+        __builtin_amdgcn_wave_barrier();
+        layer16<kHid>(my, W3t, 8, acc);
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int nt = 0; nt < 8; ++nt)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int col = nt * 16 + r, row = kq + e;
+                my[row * kHid + col] = f2bf(fmaxf(acc[nt][e] + params[L.b3 + col], 0.0f));
+            }
+        __builtin_amdgcn_s_waitcnt(0);
+        __builtin_amdgcn_wave_barrier();
+        layer16<kHid>(my, W4t, 1, acc);
+        // column 0 of the 16 x 16 result: lanes with (lane & 15) == 0 hold rows kq..kq+3
+        float z[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) z[e] = acc[0][e] + params[L.b4];
+        // broadcast: tuple row t = kq + e is held by lane (kq/4)*16 (r == 0)
+        float zr = 0.0f;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const float v = __shfl(z[e], ((lane & 15) >> 2) * 16, kWave);
+            if ((lane & 3) == e) zr = v;
+        }
+        // lanes 0..15 now hold tuple r's logit in zr (row = lane & 15)
+        const int64_t q = q0 + r;
+        const bool mine = lane < 16 && q < io.n;
+        const float p = 1.0f / (1.0f + expf(-zr));
+        if (mine && scores) scores[q] = p;
+        const bool keep = mine && p >= threshold;
+        const unsigned long long bal = __ballot(keep);
+        const int tot = __popcll(bal);
+        if (tot > 0) {
+            unsigned long long base = 0;
+            if (lane == 0) base = atomicAdd(keep_count, (unsigned long long)tot);
+            base = __shfl(base, 0, kWave);
+            if (keep) {
+                const unsigned long long o = base + __popcll(bal & ((1ull << lane) - 1ull));
+                if (o < (unsigned long long)cap) keep_idx[o] = int32_t(q);
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+static inline unsigned nblk(int64_t n, int b) { return unsigned((n + b - 1) / b); }
+
+hipError_t launch_gather(const PrunerIO& io, unsigned short* X, float* Xf, hipStream_t s)
+{
+    if (io.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather, dim3(nblk(io.n, 256)), dim3(256), 0, s, io, X, Xf);
+    return hipGetLastError();
+}
+
+hipError_t launch_prune_score(const PrunerIO& io, const float* params, float threshold, float* scores,
+                              int32_t* keep_idx, int64_t cap, unsigned long long* keep_count, hipStream_t s)
+{
+    if (io.n <= 0) return hipSuccess;
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute((const void*)k_prune_score, hipFuncAttributeMaxDynamicSharedMemorySize, kPruneLds);
+        attr = true;
+    }
+    const int64_t tiles = (io.n + 15) / 16;
+    int64_t blocks = (tiles + 3) / 4;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_prune_score, dim3(unsigned(blocks)), dim3(256), kPruneLds, s, io, params, threshold, scores,
+                       keep_idx, cap, keep_count);
+    return hipGetLastError();
+}
+
+// One forward + backward pass of a batch: loss (accumulated into *loss) and
+// gradients (written, fp32, same layout as the parameters).
+hipError_t pruner_fwd_bwd(const PrunerIO& io, const float* labels, float pos_w, const float* params, float* grads,
+                          float* loss, PrunerWork& W, hipStream_t s)
+{
+    const int64_t n = io.n;
+    const PrunerLayout L;
+    hipError_t e;
+    if ((e = launch_gather(io, W.X, nullptr, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_to_bf16, dim3(nblk(kNParams, 256)), dim3(256), 0, s, params, W.Pb, int64_t(kNParams));
+    // forward: Z1 = X W1 (W1 stored [in][out]: B(k,n) = W[k*128 + n])
+    auto gemm = [&](const unsigned short* A, int64_t sam, int64_t sak, const unsigned short* B, int64_t sbk,
+                    int64_t sbn, float* C, int ldc, int M, int N, int K, int split) {
+        GemmArgs G{A, sam, sak, B, sbk, sbn, C, ldc, M, N, K, 1.0f, 0};
+        return launch_gemm(G, split, s);
+    };
+    const int nn = int(n);
+    gemm(W.X, kFeat, 1, W.Pb + L.w1, kHid, 1, W.Z1, kHid, nn, kHid, kIn, 1);
+    hipLaunchKernelGGL(k_bias_relu, dim3(nblk(n * kHid, 256)), dim3(256), 0, s, W.Z1, params + L.b1, W.H1, n, kHid, 1);
+    gemm(W.H1, kHid, 1, W.Pb + L.w2, kHid, 1, W.Z2, kHid, nn, kHid, kHid, 1);
+    hipLaunchKernelGGL(k_bias_relu, dim3(nblk(n * kHid, 256)), dim3(256), 0, s, W.Z2, params + L.b2, W.H2, n, kHid, 1);
+    gemm(W.H2, kHid, 1, W.Pb + L.w3, kHid, 1, W.Z3, kHid, nn, kHid, kHid, 1);
+    hipLaunchKernelGGL(k_bias_relu, dim3(nblk(n * kHid, 256)), dim3(256), 0, s, W.Z3, params + L.b3, W.H3, n, kHid, 1);
+    // z4 = H3 W4 + b4 (N = 1); the bias is added inside the loss kernel
+    gemm(W.H3, kHid, 1, W.Pb + L.w4, 1, 0, W.Z4, 16, nn, 1, kHid, 1);
+    hipLaunchKernelGGL(k_loss, dim3(nblk(n, 256)), dim3(256), 0, s, W.Z4, 16, params + L.b4, labels, n, pos_w,
+                       1.0f / float(n), W.dZ4, (float*)nullptr, loss);
+    // backward
+    hipLaunchKernelGGL(k_fill, dim3(nblk(kNParams, 256)), dim3(256), 0, s, grads, int64_t(kNParams), 0.0f);
+    const int split = n >= 4096 ? 16 : 4;
+    // dW4 = H3^T dZ4 : A(m=in, k=row) = H3[row*128 + m], B(k=row, n=0) = dZ4[row*16]
+    gemm(W.H3, 1, kHid, W.dZ4, 16, 1, grads + L.w4, 1, kHid, 1, nn, split);
+    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(256), 0, s, W.dZ4, n, 1, 16, grads + L.b4);
+    // dH3 = dZ4 W4^T : A(row, k) = dZ4[row*16 + k] (k < 1), B(k, n) = W4[n*1 + k]
+    gemm(W.dZ4, 16, 1, W.Pb + L.w4, 1, 1, W.dH, kHid, nn, kHid, 1, 1);
+    hipLaunchKernelGGL(k_relu_bwd, dim3(nblk(n * kHid, 256)), dim3(256), 0, s, W.dH, W.Z3, W.dZ, n * kHid);
+    gemm(W.H2, 1, kHid, W.dZ, kHid, 1, grads + L.w3, kHid, kHid, kHid, nn, split);
+    hipLaunchKernelGGL(k_colsum, dim3(kHid), dim3(256), 0, s, W.dZ, n, kHid, kHid, grads + L.b3);
+    gemm(W.dZ, kHid, 1, W.Pb + L.w3, 1, kHid, W.dH, kHid, nn, kHid, kHid, 1);
+    hipLaunchKernelGGL(k_relu_bwd, dim3(nblk(n * kHid, 256)), dim3(256), 0, s, W.dH, W.Z2, W.dZ, n * kHid);
+    gemm(W.H1, 1, kHid, W.dZ, kHid, 1, grads + L.w2, kHid, kHid, kHid, nn, split);
+    hipLaunchKernelGGL(k_colsum, dim3(kHid), dim3(256), 0, s, W.dZ, n, kHid, kHid, grads + L.b2);
+    gemm(W.dZ, kHid, 1, W.Pb + L.w2, 1, kHid, W.dH, kHid, nn, kHid, kHid, 1);
+    hipLaunchKernelGGL(k_relu_bwd, dim3(nblk(n * kHid, 256)), dim3(256), 0, s, W.dH, W.Z1, W.dZ, n * kHid);
+    gemm(W.X, 1, kFeat, W.dZ, kHid, 1, grads + L.w1, kHid, kIn, kHid, nn, split);
+    hipLaunchKernelGGL(k_colsum, dim3(kHid), dim3(256), 0, s, W.dZ, n, kHid, kHid, grads + L.b1);
+    return hipGetLastError();
+}
+
+hipError_t pruner_adam(float* p, const float* g, float* m, float* v, int64_t step, float lr, float b1, float b2,
+                       float eps, hipStream_t s)
+{
+    const float c1 = 1.0f - powf(b1, float(step)), c2 = 1.0f - powf(b2, float(step));
+    hipLaunchKernelGGL(k_adam, dim3(nblk(kNParams, 256)), dim3(256), 0, s, p, g, m, v, int64_t(kNParams), lr, b1, b2,
+                       eps, c1, c2);
+    return hipGetLastError();
+}
+
+}  // namespace spoly

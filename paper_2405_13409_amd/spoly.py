@@ -25,7 +25,9 @@ SOLUTION_DTYPE = np.dtype([("query", "<i4"), ("tri", "<i4", (2,)), ("flags", "<u
 assert SOLUTION_DTYPE.itemsize == 56
 
 EXPORTED = ("spoly_ctx_create", "spoly_ctx_destroy", "spoly_default_params", "spoly_status_str",
-            "spoly_cull_1bounce", "spoly_solve_1bounce", "spoly_cull_2bounce", "spoly_solve_nbounce")
+            "spoly_cull_1bounce", "spoly_solve_1bounce", "spoly_cull_2bounce", "spoly_solve_nbounce",
+            "spoly_prune_score", "spoly_pruner_fwd_bwd", "spoly_pruner_step", "spoly_pruner_features")
+PRUNER_NPARAMS = 38657
 
 
 class SpolyError(RuntimeError):
@@ -81,6 +83,16 @@ def load_library(path: str = LIB_PATH):
                                       ctypes.POINTER(Points), P, P, P, I64, ctypes.c_int, ctypes.POINTER(Params), P, P,
                                       I64, P, P, P, P]
     L.spoly_solve_nbounce.restype = ctypes.c_int
+    F = ctypes.c_float
+    MP, PP = ctypes.POINTER(Mesh), ctypes.POINTER(Points)
+    L.spoly_prune_score.argtypes = [P, MP, PP, PP, P, P, P, I64, P, F, P, P, I64, P, P]
+    L.spoly_prune_score.restype = ctypes.c_int
+    L.spoly_pruner_fwd_bwd.argtypes = [P, MP, PP, PP, P, P, P, I64, P, F, P, P, P, P]
+    L.spoly_pruner_fwd_bwd.restype = ctypes.c_int
+    L.spoly_pruner_step.argtypes = [P, P, P, P, P, I64, F, F, F, F, P]
+    L.spoly_pruner_step.restype = ctypes.c_int
+    L.spoly_pruner_features.argtypes = [P, MP, PP, PP, P, P, P, I64, P, P]
+    L.spoly_pruner_features.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -263,6 +275,45 @@ def _solve_2bounce(self, mesh: DeviceMesh, x0s: DevicePoints, x3s: DevicePoints,
         cap = n
 
 
+def _pruner_features(self, mesh, x0s, x3s, q_x0, q_x3, q_tris):
+    n = int(q_x0.numel())
+    out = torch.empty(n * 48, dtype=torch.float32, device="cuda")
+    _check(load_library().spoly_pruner_features(self.h, ctypes.byref(mesh.c), ctypes.byref(x0s.c), ctypes.byref(x3s.c),
+                                                _ptr(q_x0), _ptr(q_x3), _ptr(q_tris), n, _ptr(out), _stream()),
+           "spoly_pruner_features")
+    return out.view(n, 48)
+
+
+def _pruner_fwd_bwd(self, mesh, x0s, x3s, q_x0, q_x3, q_tris, labels, pos_weight, params, grads, loss):
+    n = int(q_x0.numel())
+    _check(load_library().spoly_pruner_fwd_bwd(self.h, ctypes.byref(mesh.c), ctypes.byref(x0s.c), ctypes.byref(x3s.c),
+                                               _ptr(q_x0), _ptr(q_x3), _ptr(q_tris), n, _ptr(labels),
+                                               float(pos_weight), _ptr(params), _ptr(grads), _ptr(loss), _stream()),
+           "spoly_pruner_fwd_bwd")
+
+
+def _pruner_step(self, params, grads, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    _check(load_library().spoly_pruner_step(self.h, _ptr(params), _ptr(grads), _ptr(m), _ptr(v), int(step),
+                                            float(lr), float(b1), float(b2), float(eps), _stream()),
+           "spoly_pruner_step")
+
+
+def _prune_score(self, mesh, x0s, x3s, q_x0, q_x3, q_tris, params, threshold, scores=None, keep=None,
+                 keep_count=None):
+    n = int(q_x0.numel())
+    kp = keep if keep is not None else torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+    kc = keep_count if keep_count is not None else torch.zeros(1, dtype=torch.int64, device="cuda")
+    _check(load_library().spoly_prune_score(self.h, ctypes.byref(mesh.c), ctypes.byref(x0s.c), ctypes.byref(x3s.c),
+                                            _ptr(q_x0), _ptr(q_x3), _ptr(q_tris), n, _ptr(params), float(threshold),
+                                            _ptr(scores), _ptr(kp), kp.numel(), _ptr(kc), _stream()),
+           "spoly_prune_score")
+    return kp, kc
+
+
+Context.pruner_features = _pruner_features
+Context.pruner_fwd_bwd = _pruner_fwd_bwd
+Context.pruner_step = _pruner_step
+Context.prune_score = _prune_score
 Context.cull_2bounce = _cull_2bounce
 Context.solve_2bounce = _solve_2bounce
 

@@ -1,0 +1,113 @@
+"""GPU pruner kernels (bf16 MFMA, fp32 accumulate) against the FP64 CPU twin."""
+import numpy as np
+import pytest
+import torch
+
+import mlp
+from paper_2405_13409_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sp():
+    from paper_2405_13409_amd import spoly
+
+    spoly.load_library()
+    return spoly
+
+
+@pytest.fixture(scope="module")
+def ctx(sp):
+    c = sp.Context(0)
+    yield c
+    c.close()
+
+
+def _batch(n, seed):
+    mesh = scenes.caustic_sphere()
+    R = scenes.caustic_receivers()
+    x3 = scenes.CAUSTIC_LIGHT_OUTSIDE
+    rng = np.random.default_rng(seed)
+    q0 = rng.integers(0, len(R), n).astype(np.int32)
+    q3 = np.zeros(n, dtype=np.int32)
+    qt = rng.integers(0, mesh.nt, (n, 2)).astype(np.int32)
+    y = (rng.random(n) < 0.1).astype(np.float32)
+    return mesh, R, x3, q0, q3, qt, y
+
+
+def _dev(sp, mesh, R, x3, q0, q3, qt):
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    return sp.DeviceMesh(mesh.P, mesh.N, mesh.tri), sp.DevicePoints(R), sp.DevicePoints(x3), t(q0), t(q3), t(qt)
+
+
+def test_features_match_twin(sp, ctx):
+    print("[gpu-case] pruner features", flush=True)
+    mesh, R, x3, q0, q3, qt, y = _batch(1000, 1)
+    dm, dR, d3, t0, t3, tt = _dev(sp, mesh, R, x3, q0, q3, qt)
+    f = ctx.pruner_features(dm, dR, d3, t0, t3, tt).cpu().numpy()
+    ref = mlp.features(mesh.P, mesh.N, mesh.tri, R, x3, q0, q3, qt)
+    assert np.allclose(f[:, :42], ref.astype(np.float32), rtol=0, atol=1e-7)
+    assert np.all(f[:, 42:] == 0)
+
+
+@pytest.mark.parametrize("n", [100, 4096])
+def test_forward_backward_vs_fp64_twin(sp, ctx, n):
+    print(f"[gpu-case] pruner fwd/bwd n={n}", flush=True)
+    mesh, R, x3, q0, q3, qt, y = _batch(n, 2)
+    dm, dR, d3, t0, t3, tt = _dev(sp, mesh, R, x3, q0, q3, qt)
+    p = mlp.init_params(3)
+    X = mlp.features(mesh.P, mesh.N, mesh.tri, R, x3, q0, q3, qt)
+    # the GPU sees bf16 inputs and weights: compare against the twin on the same rounded values
+    bf = lambda a: torch.from_numpy(a.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()  # noqa: E731
+    loss_ref, g_ref = mlp.loss_and_grad(p, bf(X), y.astype(np.float64), 5.0)
+    params = torch.from_numpy(p.astype(np.float32)).cuda()
+    grads = torch.zeros_like(params)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    ctx.pruner_fwd_bwd(dm, dR, d3, t0, t3, tt, torch.from_numpy(y).cuda(), 5.0, params, grads, loss)
+    torch.cuda.synchronize()
+    g = grads.cpu().numpy().astype(np.float64)
+    assert abs(loss.item() - loss_ref) <= 2e-2 * abs(loss_ref)
+    G, Gr = mlp.unpack(g), mlp.unpack(g_ref)
+    for name, _ in mlp.SIZES:
+        a, b = G[name].ravel(), Gr[name].ravel()
+        rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+        print(name, rel)
+        assert rel <= 2e-2, (name, rel)
+
+
+def test_score_kernel_vs_twin(sp, ctx):
+    print("[gpu-case] pruner score", flush=True)
+    mesh, R, x3, q0, q3, qt, y = _batch(5000, 4)
+    dm, dR, d3, t0, t3, tt = _dev(sp, mesh, R, x3, q0, q3, qt)
+    p = mlp.init_params(5)
+    X = mlp.features(mesh.P, mesh.N, mesh.tri, R, x3, q0, q3, qt)
+    z, _ = mlp.forward(p, X)
+    pref = 1 / (1 + np.exp(-z))
+    params = torch.from_numpy(p.astype(np.float32)).cuda()
+    scores = torch.zeros(len(q0), dtype=torch.float32, device="cuda")
+    thr = float(np.median(pref))
+    keep, kc = ctx.prune_score(dm, dR, d3, t0, t3, tt, params, thr, scores=scores)
+    torch.cuda.synchronize()
+    s = scores.cpu().numpy()
+    assert np.max(np.abs(s - pref)) < 3e-2
+    kept = np.sort(keep[: int(kc.item())].cpu().numpy())
+    assert np.array_equal(kept, np.nonzero(s >= thr)[0])
+
+
+def test_adam_step_matches_reference(sp, ctx):
+    print("[gpu-case] adam", flush=True)
+    rng = np.random.default_rng(6)
+    p = rng.normal(size=mlp.NPARAMS).astype(np.float32)
+    g = rng.normal(size=mlp.NPARAMS).astype(np.float32)
+    P, G = torch.from_numpy(p.copy()).cuda(), torch.from_numpy(g).cuda()
+    m, v = torch.zeros_like(P), torch.zeros_like(P)
+    for step in (1, 2):
+        ctx.pruner_step(P, G, m, v, step, 1e-3, 0.9, 0.999, 1e-8)
+    torch.cuda.synchronize()
+    mm, vv, pp = np.zeros_like(p, dtype=np.float64), np.zeros_like(p, dtype=np.float64), p.astype(np.float64)
+    for step in (1, 2):
+        mm = 0.9 * mm + 0.1 * g
+        vv = 0.999 * vv + 0.001 * g.astype(np.float64) ** 2
+        pp = pp - 1e-3 * (mm / (1 - 0.9 ** step)) / (np.sqrt(vv / (1 - 0.999 ** step)) + 1e-8)
+    assert np.max(np.abs(P.cpu().numpy() - pp)) < 1e-5
