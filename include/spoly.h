@@ -59,8 +59,9 @@ typedef enum { SPOLY_R = 0, SPOLY_T = 1 } spoly_event;
 /* arithmetic of the bulk stages; the final polish and validation are always FP64 */
 typedef enum {
     SPOLY_FP64 = 0,          /* every stage in double precision                           */
-    SPOLY_FP32_POLISH64 = 1  /* coefficients, elimination and root isolation in float;   */
-                             /* root polish, path phase and validation in double          */
+    SPOLY_FP32_POLISH64 = 1  /* R: coefficients, elimination and root isolation in float; */
+                             /* root polish, path phase and validation in double.  T and  */
+                             /* TT run every stage in double under either value.          */
 } spoly_precision;
 
 /* Triangle mesh, structure of arrays.  px..pz: vertex positions, nx..nz: vertex

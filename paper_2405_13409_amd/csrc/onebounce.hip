@@ -299,24 +299,9 @@ __device__ __forceinline__ void solve_instance(const Geo& g, const OneBounceArgs
     using Y = Sys<R, EV, F>;
     P2<R, Y::TA> a;
     P2<R, Y::TB> b;
-    if constexpr (EV == SPOLY_T && sizeof(R) == 4) {
-        // The square form is a difference of two nearly equal squares over a
-        // small triangle; its coefficients are built in FP64 and rounded to FP32
-        // only after normalisation.
-        P2<double, Y::TA> a64;
-        P2<double, Y::TB> b64;
-        build_ab<double, EV, F>(g, A.eta0, A.eta1, a64, b64);
-        normalise(a64);
-        normalise(b64);
-#pragma unroll
-        for (int k = 0; k < tri_size(Y::TA); ++k) a.c[k] = R(a64.c[k]);
-#pragma unroll
-        for (int k = 0; k < tri_size(Y::TB); ++k) b.c[k] = R(b64.c[k]);
-    } else {
-        build_ab<R, EV, F>(g, A.eta0, A.eta1, a, b);
-        normalise(a);
-        normalise(b);
-    }
+    build_ab<R, EV, F>(g, A.eta0, A.eta1, a, b);
+    normalise(a);
+    normalise(b);
     R r[Y::DR + 1];
     eliminate<R, EV, F>(a.c, b.c, r);
     R rmax = R(0);
@@ -487,10 +472,13 @@ hipError_t launch_onebounce(const OneBounceArgs& A, int ev, int prec, hipStream_
 {
     if (A.nq <= 0) return hipSuccess;
     dim3 block(256), grid(unsigned((A.nq + 255) / 256));
+    // Refraction always runs in FP64: its degree-12 resultant, expanded and
+    // isolated in FP32, loses roots of the square form (a difference of two
+    // nearly equal squares over a small triangle), while FP32 and FP64 have the
+    // same non-packed VALU rate on this chip.
     if (ev == SPOLY_R && prec == SPOLY_FP64) hipLaunchKernelGGL((k_onebounce<double, SPOLY_R>), grid, block, 0, stream, A);
     else if (ev == SPOLY_R) hipLaunchKernelGGL((k_onebounce<float, SPOLY_R>), grid, block, 0, stream, A);
-    else if (prec == SPOLY_FP64) hipLaunchKernelGGL((k_onebounce<double, SPOLY_T>), grid, block, 0, stream, A);
-    else hipLaunchKernelGGL((k_onebounce<float, SPOLY_T>), grid, block, 0, stream, A);
+    else hipLaunchKernelGGL((k_onebounce<double, SPOLY_T>), grid, block, 0, stream, A);
     return hipGetLastError();
 }
 

@@ -432,7 +432,7 @@ hipError_t pruner_fwd_bwd(const PrunerIO& io, const float* labels, float pos_w, 
                        1.0f / float(n), W.dZ4, (float*)nullptr, loss);
     // backward
     hipLaunchKernelGGL(k_fill, dim3(nblk(kNParams, 256)), dim3(256), 0, s, grads, int64_t(kNParams), 0.0f);
-    const int split = n >= 4096 ? 16 : 4;
+    const int split = 1;   // no atomics: the gradients, hence training, are deterministic
     // dW4 = H3^T dZ4 : A(m=in, k=row) = H3[row*128 + m], B(k=row, n=0) = dZ4[row*16]
     gemm(W.H3, 1, kHid, W.dZ4, 16, 1, grads + L.w4, 1, kHid, 1, nn, split);
     hipLaunchKernelGGL(k_colsum, dim3(1), dim3(256), 0, s, W.dZ4, n, 1, 16, grads + L.b4);
