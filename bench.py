@@ -4,12 +4,12 @@ Workload (one step = the whole hot path over one batch): a 128x128 heightfield
 (32768 triangles, z = 0.02 * 8 sinusoids of angular frequency 4..32), 256x256
 shading points at z = 2 (reflection) and at z = -2 (refraction, IOR 1.5 below
 the surface), one point light at (0, 0, 4).  A step runs, for R and for T:
-S0 cone cull over all 65536 x 32768 (point, triangle) pairs, then S1-S7 on the
-kept candidates (coefficients, Bezout + Laplace, isolation, u solve, FP64
+the normal-cone cull over all 65536 x 32768 (point, triangle) pairs, then the
+full solve on the kept candidates (coefficients, Bezout + Laplace, isolation, u solve, FP64
 polish, validation, compaction).  Inputs are resident in HBM before timing.
 
-Prints one JSON line.  value = candidate solves / s (candidates entering S1 per
-second of step time); valid paths / s is reported beside it.
+Prints one JSON line.  value = candidate solves / s (candidates entering the
+solve per second of step time); valid paths / s is reported beside it.
 """
 from __future__ import annotations
 
@@ -223,7 +223,7 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"glints: 128x128 heightfield (32768 tris), {args.res}x{args.res} points at z=+2 (R) and "
-                        f"z=-2 (T, IOR 1.5), light (0,0,4); S0 cone cull of all pairs + S1-S7 solve",
+                        f"z=-2 (T, IOR 1.5), light (0,0,4); cone cull of all pairs + full solve",
             "precision": "fp32 bulk, fp64 polish" if args.precision == "fp32" else "fp64",
             "candidates_per_step": inst // args.steps,
             "valid_paths_per_step": sols // args.steps,

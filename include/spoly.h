@@ -114,14 +114,18 @@ spoly_status spoly_ctx_create(spoly_ctx **ctx, int device);
 /* Free the context and all device memory it owns.  NULL is ignored. */
 void spoly_ctx_destroy(spoly_ctx *ctx);
 
-/* Fill *p [host] with the default parameters. */
+/* Fill *p [host] with the default parameters (one-vertex u margin 1e-4). */
 void spoly_default_params(spoly_params *p);
+/* The same defaults with the two-vertex u margin 0.05: the first vertex's u
+ * range is widened because the sqrt approximation of Eq. eq_refr_rational
+ * moves the approximate roots before the FP64 polish. */
+void spoly_tt_default_params(spoly_params *p);
 
 /* Human-readable name of a status code (static storage). */
 const char *spoly_status_str(spoly_status s);
 
 /*
- * S0 -- conservative normal-cone cull for one specular vertex.
+ * Conservative normal-cone cull for one specular vertex.
  * For every (x0 in x0s, x2 in x2s, triangle) triple, keep it unless no
  * generalised half vector h = eta0 w0 + eta1 w2 (w0, w2 unit directions from a
  * point of the triangle to x0 and x2) can be parallel to an interpolated normal
@@ -145,7 +149,8 @@ spoly_status spoly_cull_1bounce(spoly_ctx *ctx, const spoly_mesh *mesh,
                                 int64_t out_capacity, unsigned long long *out_count, void *stream);
 
 /*
- * S1-S7 for one specular vertex (Sec. 4.5 systems R and T).
+ * Full solve (coefficients, elimination, isolation, polish, validation) for
+ * one specular vertex (Sec. 4.5 systems R and T).
  * Query q solves the chain x0s[q_x0[q]] -> triangle q_tri[q] -> x2s[q_x2[q]].
  * eta0: IOR of the medium of x0, eta1: IOR of the medium of x2 (Eq. eq_ch;
  * reflection uses eta0 = eta1).  R requires both endpoints on the same side of
@@ -168,7 +173,7 @@ spoly_status spoly_solve_1bounce(spoly_ctx *ctx, const spoly_mesh *mesh,
                                  int32_t *diag_q, void *stream);
 
 /*
- * S0 for two specular vertices (chain x0 -> T1 -> T2 -> x3).
+ * Normal-cone cull for two specular vertices (chain x0 -> T1 -> T2 -> x3).
  * For every x0 in x0s, x3 in x3s and ordered pair of distinct triangles, keep
  * the tuple unless one vertex fails the half-vector / normal-cone test of
  * spoly_cull_1bounce: at x1 the half vector combines the direction to x0
@@ -188,7 +193,7 @@ spoly_status spoly_cull_2bounce(spoly_ctx *ctx, const spoly_mesh *mesh,
                                 int64_t out_capacity, unsigned long long *out_count, void *stream);
 
 /*
- * S1-S7 for k = 2 specular vertices (Sec. 4.4-4.5, Sec. 5.2): chain [host, k]
+ * Full solve for k = 2 specular vertices (Sec. 4.4-4.5, Sec. 5.2): chain [host, k]
  * must be {SPOLY_T, SPOLY_T}; eta [host, k+1] = IORs of the segments x0x1,
  * x1x2, x2x3 (Eq. eq_ch).  Query q solves x0s[q_x0[q]] -> triangle q_tris[2q]
  * -> triangle q_tris[2q+1] -> x3s[q_x3[q]].
@@ -196,7 +201,9 @@ spoly_status spoly_cull_2bounce(spoly_ctx *ctx, const spoly_mesh *mesh,
  * Sec. 4.4: sqrt_table [host, optional] = 7 piece ends then (c0, c1, d0, d1)
  * for each of the 6 pieces; NULL selects the library's minimax table.  The
  * sign of det R(v) is sampled at v = j/pieces (pieces <= 127) and each sign
- * change is bisected bisect_iters times; every candidate is polished in FP64 on
+ * change is refined to 2^-bisect_iters of its width (bisect_iters <= 10, the
+ * dyadic lattice of that many bisection steps, searched in two wave-wide
+ * rounds); every candidate is polished in FP64 on
  * the exact refraction constraints (the approximation only brackets roots).
  * prec must be SPOLY_FP64.  Records carry tri[0..1] and (u,v) of both vertices.
  * counters / diag_q as for spoly_solve_1bounce ([0] counts sign changes).
@@ -211,7 +218,7 @@ spoly_status spoly_solve_nbounce(spoly_ctx *ctx, const spoly_mesh *mesh, int32_t
                                  unsigned long long *counters, int32_t *diag_q, void *stream);
 
 /*
- * S8 -- learned pruner of two-vertex tuples (callers who want to skip tuples
+ * Learned pruner of two-vertex tuples (callers who want to skip tuples
  * that cannot hold a path before spoly_solve_nbounce).  An MLP with 42 inputs
  * (x0/2, x3/2, the positions of T1 and T2 divided by 2, the vertex normals of
  * T1 and T2), three hidden layers of 128 ReLU units and a sigmoid output.
@@ -250,6 +257,36 @@ spoly_status spoly_pruner_step(spoly_ctx *ctx, float *params, const float *grads
 spoly_status spoly_pruner_features(spoly_ctx *ctx, const spoly_mesh *mesh, const spoly_points *x0s,
                                    const spoly_points *x3s, const int32_t *q_x0, const int32_t *q_x3,
                                    const int32_t *q_tris, int64_t n, float *features, void *stream);
+
+/*
+ * Mixed batches in one persistent launch.  Work items are tiles of
+ * `r_tile` one-vertex instances (problem 1, as spoly_solve_1bounce) and single
+ * two-vertex tuples (problem 2, as spoly_solve_nbounce with chain TT); waves
+ * take items from the device counter *queue (zeroed by the caller) until it
+ * passes the last item.  Output records of problem 1 carry query q, those of
+ * problem 2 carry n1 + q.  prec applies to problem 1's R bulk (T and TT run in
+ * FP64).  params->u_margin applies to problem 1; problem 2 searches u on
+ * [-0.05, 1-v+0.05], the margin spoly_tt_default_params sets.  Shapes come
+ * from spoly_mixed_shape (an autotuner may choose them).  Errors as
+ * spoly_solve_1bounce; a shape outside the stated ranges is E_INVALID_ARG.
+ */
+typedef struct {
+    int32_t workgroups_per_cu;  /* persistent grid = compute units x this (1..32)          */
+    int32_t r_tile;             /* one-vertex instances per work item (64..4096, x64)       */
+    int32_t order;              /* 0: two-vertex items first, 1: one-vertex first, 2: mixed */
+    int32_t pad;
+} spoly_mixed_shape;
+
+spoly_status spoly_solve_mixed(spoly_ctx *ctx,
+                               const spoly_mesh *mesh1, const spoly_points *x0s1, const spoly_points *x2s1,
+                               const int32_t *q1_x0, const int32_t *q1_x2, const int32_t *q1_tri, int64_t n1,
+                               spoly_event ev1, double eta0, double eta1,
+                               const spoly_mesh *mesh2, const spoly_points *x0s2, const spoly_points *x3s2,
+                               const int32_t *q2_x0, const int32_t *q2_x3, const int32_t *q2_tris, int64_t n2,
+                               const double *eta2, spoly_precision prec, const spoly_params *params,
+                               const spoly_mixed_shape *shape, unsigned long long *queue,
+                               spoly_solution *out, int64_t out_capacity, unsigned long long *out_count,
+                               void *stream);
 
 #ifdef __cplusplus
 }

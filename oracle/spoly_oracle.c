@@ -1021,7 +1021,7 @@ int or_det_sign(const double *a_in, int32_t da, const double *b_in, int32_t db, 
 
 int or_maxsol(void) { return OR_MAXSOL; }
 
-/* ================================================================== S0 twin: normal-cone cull (FP64)
+/* ================================================================== Normal-cone cull twin (FP64)
  * keep[(j0*n2 + j2)*nt + t] = 1 unless the cone of generalised half vectors
  * h = eta0 w0 + eta1 w2 (w0, w2: unit directions from a point of the
  * triangle's bounding sphere to x0 and x2) cannot meet the cone of the vertex
@@ -1070,7 +1070,7 @@ int or_cull_1bounce(const double *P, const double *N, const int32_t *tri, int64_
     return 0;
 }
 
-/* ================================================================== S0 twin for two vertices (FP64)
+/* ================================================================== Normal-cone cull twin for two vertices (FP64)
  * Tuple (x0, T1, T2, x3) is kept unless one of the two vertices fails the
  * half-vector / normal-cone test of or_cull_1bounce: at x1 the directions go to
  * x0 (eta[0]) and into the cone from T1 to T2 (eta[1]); at x2 they go into

@@ -6,7 +6,6 @@ square-root approximation table (sqrtfit.py -> csrc/sqrt_table.inc).
 """
 from __future__ import annotations
 
-import glob
 import os
 import subprocess
 import sys
@@ -42,7 +41,8 @@ def generate() -> None:
 
 
 def sources():
-    return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    """The unity translation unit; it includes every module under csrc/."""
+    return [os.path.join(CSRC, "libspoly.hip")]
 
 
 def build(verbose: bool = False) -> str:

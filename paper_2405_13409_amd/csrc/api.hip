@@ -10,6 +10,7 @@
 #include "twobounce.hpp"
 #include "sqrt_table.inc"
 #include "pruner.hpp"
+#include "mixed.hpp"
 
 struct spoly_ctx {
     int device;
@@ -47,6 +48,13 @@ void spoly_default_params(spoly_params* p)
     p->dedup = 1e-8;
     p->polish_iters = 6;
     p->flags = 0;
+}
+
+void spoly_tt_default_params(spoly_params* p)
+{
+    if (!p) return;
+    spoly_default_params(p);
+    p->u_margin = 0.05;
 }
 
 const char* spoly_status_str(spoly_status s)
@@ -220,7 +228,8 @@ spoly_status spoly_solve_nbounce(spoly_ctx* ctx, const spoly_mesh* mesh, int32_t
     if (chain[0] != SPOLY_T || chain[1] != SPOLY_T) return SPOLY_E_UNSUPPORTED;
     if (prec != SPOLY_FP64) return SPOLY_E_UNSUPPORTED;
     if (!(eta[0] > 0.0) || !(eta[1] > 0.0) || !(eta[2] > 0.0)) return SPOLY_E_INVALID_ARG;
-    if (params->pieces < 1 || params->pieces > 127 || params->bisect_iters < 0 || params->polish_iters < 0 ||
+    if (params->pieces < 1 || params->pieces > 127 || params->bisect_iters < 0 || params->bisect_iters > 10 ||
+        params->polish_iters < 0 ||
         !(params->tau > 0.0) || !(params->u_margin >= 0.0) || !(params->dedup >= 0.0))
         return SPOLY_E_INVALID_ARG;
     if (hipSetDevice(ctx->device) != hipSuccess) return SPOLY_E_DEVICE;
@@ -347,3 +356,74 @@ spoly_status spoly_pruner_features(spoly_ctx* ctx, const spoly_mesh* mesh, const
 }
 
 }  // extern "C"
+
+extern "C" spoly_status spoly_solve_mixed(spoly_ctx* ctx, const spoly_mesh* mesh1, const spoly_points* x0s1,
+                                         const spoly_points* x2s1, const int32_t* q1_x0, const int32_t* q1_x2,
+                                         const int32_t* q1_tri, int64_t n1, spoly_event ev1, double eta0,
+                                         double eta1, const spoly_mesh* mesh2, const spoly_points* x0s2,
+                                         const spoly_points* x3s2, const int32_t* q2_x0, const int32_t* q2_x3,
+                                         const int32_t* q2_tris, int64_t n2, const double* eta2,
+                                         spoly_precision prec, const spoly_params* params,
+                                         const spoly_mixed_shape* shape, unsigned long long* queue,
+                                         spoly_solution* out, int64_t out_capacity, unsigned long long* out_count,
+                                         void* stream)
+{
+    if (!ctx || !params || !shape || !queue || !out_count || !eta2) return SPOLY_E_INVALID_ARG;
+    if (!mesh_ok(mesh1) || !pts_ok(x0s1) || !pts_ok(x2s1) || !mesh_ok(mesh2) || !pts_ok(x0s2) || !pts_ok(x3s2))
+        return SPOLY_E_INVALID_ARG;
+    if (n1 < 0 || n2 < 0 || out_capacity < 0 || (out_capacity > 0 && !out)) return SPOLY_E_INVALID_ARG;
+    if ((n1 > 0 && (!q1_x0 || !q1_x2 || !q1_tri)) || (n2 > 0 && (!q2_x0 || !q2_x3 || !q2_tris)))
+        return SPOLY_E_INVALID_ARG;
+    if (ev1 != SPOLY_R && ev1 != SPOLY_T) return SPOLY_E_INVALID_ARG;
+    if (prec != SPOLY_FP64 && prec != SPOLY_FP32_POLISH64) return SPOLY_E_INVALID_ARG;
+    if (!(eta0 > 0.0) || !(eta1 > 0.0) || !(eta2[0] > 0.0) || !(eta2[1] > 0.0) || !(eta2[2] > 0.0))
+        return SPOLY_E_INVALID_ARG;
+    if (shape->workgroups_per_cu < 1 || shape->workgroups_per_cu > 32 || shape->r_tile < 64 ||
+        shape->r_tile > 4096 || (shape->r_tile % 64) != 0 || shape->order < 0 || shape->order > 2)
+        return SPOLY_E_INVALID_ARG;
+    if (params->pieces < 1 || params->pieces > 127 || params->bisect_iters < 0 || params->bisect_iters > 10 ||
+        params->polish_iters < 0 || !(params->tau > 0.0) || !(params->iso_eps > 0.0) || !(params->u_margin >= 0.0) ||
+        !(params->dedup >= 0.0))
+        return SPOLY_E_INVALID_ARG;
+    if (n1 + n2 > 2147483647LL) return SPOLY_E_INVALID_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess) return SPOLY_E_DEVICE;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || cus <= 0)
+        return SPOLY_E_DEVICE;
+    spoly::MixedArgs M;
+    spoly::OneBounceArgs& A = M.r;
+    A.px = mesh1->px; A.py = mesh1->py; A.pz = mesh1->pz;
+    A.nx = mesh1->nx; A.ny = mesh1->ny; A.nz = mesh1->nz;
+    A.tri = mesh1->tri;
+    A.x0x = x0s1->x; A.x0y = x0s1->y; A.x0z = x0s1->z;
+    A.x2x = x2s1->x; A.x2y = x2s1->y; A.x2z = x2s1->z;
+    A.q_x0 = q1_x0; A.q_x2 = q1_x2; A.q_tri = q1_tri;
+    A.nq = n1;
+    A.eta0 = eta0; A.eta1 = eta1;
+    A.iso_eps = params->iso_eps; A.tau = params->tau; A.u_margin = params->u_margin; A.dedup = params->dedup;
+    A.polish_iters = params->polish_iters;
+    A.out = out; A.cap = out_capacity; A.out_count = out_count;
+    A.counters = nullptr; A.diag_q = nullptr;
+    spoly::TTArgs& T = M.t;
+    T.px = mesh2->px; T.py = mesh2->py; T.pz = mesh2->pz;
+    T.nx = mesh2->nx; T.ny = mesh2->ny; T.nz = mesh2->nz;
+    T.tri = mesh2->tri;
+    T.x0x = x0s2->x; T.x0y = x0s2->y; T.x0z = x0s2->z;
+    T.x3x = x3s2->x; T.x3y = x3s2->y; T.x3z = x3s2->z;
+    T.q_x0 = q2_x0; T.q_x3 = q2_x3; T.q_tris = q2_tris;
+    T.nq = n2;
+    T.eta0 = eta2[0]; T.eta1 = eta2[1]; T.eta2 = eta2[2];
+    for (int i = 0; i < 7; ++i) T.sqrt_bp[i] = kSqrtPieceEnds[i];
+    for (int i = 0; i < 24; ++i) T.sqrt_c[i] = kSqrtCoef[i];
+    T.pieces = params->pieces; T.bisect_iters = params->bisect_iters; T.polish_iters = params->polish_iters;
+    T.tau = params->tau; T.u_margin = 0.05; T.dedup = params->dedup;
+    T.out = out; T.cap = out_capacity; T.out_count = out_count;
+    T.counters = nullptr; T.diag_q = nullptr;
+    M.r_tile = shape->r_tile;
+    M.order = shape->order;
+    M.n_r_tiles = (n1 + shape->r_tile - 1) / shape->r_tile;
+    M.n_items = M.n_r_tiles + n2;
+    M.queue = queue;
+    return dev_err(spoly::launch_mixed(M, int(ev1), int(prec), cus * shape->workgroups_per_cu,
+                                       static_cast<hipStream_t>(stream)));
+}

@@ -1,4 +1,4 @@
-// S0: conservative normal-cone cull of (x0, x2, triangle) triples for one
+// Conservative normal-cone cull of (x0, x2, triangle) triples for one
 // specular vertex.  h x n = 0 (Eq. eq_ch) needs the generalised half vector
 // h = eta0 w0 + eta2 w2 to be parallel to the interpolated normal; the kernel
 // rejects a triple only when the cone of possible h directions and the cone of

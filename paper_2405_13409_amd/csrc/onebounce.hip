@@ -387,11 +387,11 @@ __device__ __forceinline__ V3<double> ld3(const double* x, const double* y, cons
     return {x[i], y[i], z[i]};
 }
 
+// One instance per lane; every lane of the wave must call it (the compaction
+// is wave-wide).  Output records carry query id q + qid_offset.
 template <typename R, int EV>
-__global__ void __launch_bounds__(256) k_onebounce(OneBounceArgs A)
+__device__ __forceinline__ void onebounce_lane(const OneBounceArgs& A, int64_t q, bool active, int64_t qid_offset)
 {
-    const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    const bool active = q < A.nq;
     LaneSols S;
     S.n = 0;
     int nvr = 0, ncand = 0, degen = 0;
@@ -438,7 +438,7 @@ __global__ void __launch_bounds__(256) k_onebounce(OneBounceArgs A)
             unsigned long long idx = first + k;
             if (idx < (unsigned long long)A.cap) {
                 spoly_solution s;
-                s.query = int32_t(q);
+                s.query = int32_t(q + qid_offset);
                 s.tri[0] = tid;
                 s.tri[1] = -1;
                 s.flags = 0;
@@ -466,6 +466,13 @@ __global__ void __launch_bounds__(256) k_onebounce(OneBounceArgs A)
         A.diag_q[2 * q] = nvr;
         A.diag_q[2 * q + 1] = S.n;
     }
+}
+
+template <typename R, int EV>
+__global__ void __launch_bounds__(256) k_onebounce(OneBounceArgs A)
+{
+    const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    onebounce_lane<R, EV>(A, q, q < A.nq, 0);
 }
 
 hipError_t launch_onebounce(const OneBounceArgs& A, int ev, int prec, hipStream_t stream)

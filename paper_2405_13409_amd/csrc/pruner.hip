@@ -1,4 +1,4 @@
-// S8: learned pruner of two-vertex tuples.  An MLP 42 -> 128 -> 128 -> 128 -> 1
+// Learned pruner of two-vertex tuples.  An MLP 42 -> 128 -> 128 -> 128 -> 1
 // (ReLU, sigmoid) scores each (x0, T1, T2, x3) tuple from the separators and
 // the positions / normals of both triangles; tuples scoring below a
 // calibrated threshold are not sent to the solver.  Dense layers run on the
@@ -414,10 +414,12 @@ hipError_t pruner_fwd_bwd(const PrunerIO& io, const float* labels, float pos_w, 
     if ((e = launch_gather(io, W.X, nullptr, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_to_bf16, dim3(nblk(kNParams, 256)), dim3(256), 0, s, params, W.Pb, int64_t(kNParams));
     // forward: Z1 = X W1 (W1 stored [in][out]: B(k,n) = W[k*128 + n])
+    hipError_t first_err = hipSuccess;
     auto gemm = [&](const unsigned short* A, int64_t sam, int64_t sak, const unsigned short* B, int64_t sbk,
                     int64_t sbn, float* C, int ldc, int M, int N, int K, int split) {
         GemmArgs G{A, sam, sak, B, sbk, sbn, C, ldc, M, N, K, 1.0f, 0};
-        return launch_gemm(G, split, s);
+        const hipError_t r = launch_gemm(G, split, s);
+        if (r != hipSuccess && first_err == hipSuccess) first_err = r;
     };
     const int nn = int(n);
     gemm(W.X, kFeat, 1, W.Pb + L.w1, kHid, 1, W.Z1, kHid, nn, kHid, kIn, 1);
@@ -449,7 +451,7 @@ hipError_t pruner_fwd_bwd(const PrunerIO& io, const float* labels, float pos_w, 
     hipLaunchKernelGGL(k_relu_bwd, dim3(nblk(n * kHid, 256)), dim3(256), 0, s, W.dH, W.Z1, W.dZ, n * kHid);
     gemm(W.X, 1, kFeat, W.dZ, kHid, 1, grads + L.w1, kHid, kIn, kHid, nn, split);
     hipLaunchKernelGGL(k_colsum, dim3(kHid), dim3(256), 0, s, W.dZ, n, kHid, kHid, grads + L.b1);
-    return hipGetLastError();
+    return first_err != hipSuccess ? first_err : hipGetLastError();
 }
 
 hipError_t pruner_adam(float* p, const float* g, float* m, float* v, int64_t step, float lr, float b1, float b2,

@@ -1,4 +1,4 @@
-// Learned pruner (S8): parameter layout, work buffers and launchers.
+// Learned pruner: parameter layout, work buffers and launchers.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>

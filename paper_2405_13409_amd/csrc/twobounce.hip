@@ -35,7 +35,7 @@ struct TTGeo {
     int f1, f2;                                 // 1 = interpolated normals, 0 = flat
 };
 
-__device__ __forceinline__ V3<double> ld3(const double* x, const double* y, const double* z, int i)
+__device__ __forceinline__ V3<double> ld3t(const double* x, const double* y, const double* z, int i)
 {
     return {x[i], y[i], z[i]};
 }
@@ -61,10 +61,10 @@ __device__ void tt_setup(const TTArgs& A, int64_t q, TTGeo& g)
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         int i = A.tri[3 * t1 + k], j = A.tri[3 * t2 + k];
-        P[k] = ld3(A.px, A.py, A.pz, i);
-        Nn[k] = ld3(A.nx, A.ny, A.nz, i);
-        P[3 + k] = ld3(A.px, A.py, A.pz, j);
-        Nn[3 + k] = ld3(A.nx, A.ny, A.nz, j);
+        P[k] = ld3t(A.px, A.py, A.pz, i);
+        Nn[k] = ld3t(A.nx, A.ny, A.nz, i);
+        P[3 + k] = ld3t(A.px, A.py, A.pz, j);
+        Nn[3 + k] = ld3t(A.nx, A.ny, A.nz, j);
     }
     g.p1 = P[0]; g.e11 = P[1] - P[0]; g.e12 = P[2] - P[0];
     g.n10 = Nn[0]; g.dn11 = Nn[1] - Nn[0]; g.dn12 = Nn[2] - Nn[0];
@@ -73,8 +73,8 @@ __device__ void tt_setup(const TTArgs& A, int64_t q, TTGeo& g)
     auto same = [](V3<double> a, V3<double> b) { return a.x == b.x && a.y == b.y && a.z == b.z; };
     g.f1 = (same(Nn[0], Nn[1]) && same(Nn[0], Nn[2])) ? 0 : 1;
     g.f2 = (same(Nn[3], Nn[4]) && same(Nn[3], Nn[5])) ? 0 : 1;
-    g.x0 = ld3(A.x0x, A.x0y, A.x0z, A.q_x0[q]);
-    g.x3 = ld3(A.x3x, A.x3y, A.x3z, A.q_x3[q]);
+    g.x0 = ld3t(A.x0x, A.x0y, A.x0z, A.q_x0[q]);
+    g.x3 = ld3t(A.x3x, A.x3y, A.x3z, A.q_x3[q]);
     g.eta0 = A.eta0; g.eta1 = A.eta1; g.eta2 = A.eta2;
     g.etap = A.eta0 / A.eta1;
     // per-tuple constants of the square-root approximation at the centroid of T1:
@@ -579,12 +579,10 @@ __device__ __forceinline__ bool law(V3<double> xp, V3<double> x, V3<double> xn, 
 }
 
 // ------------------------------------------------------------------ the fused kernel
-__global__ void __launch_bounds__(64) k_tt_solve(TTArgs A)
+// One tuple per wave (the whole wave must call it); `lds` holds kLdsDoubles
+// doubles private to the wave.  Output records carry query id q + qid_offset.
+__device__ __forceinline__ void tt_tuple(const TTArgs& A, int64_t q, double* lds, int64_t qid_offset)
 {
-    __shared__ double lds[kLdsDoubles];
-    __shared__ unsigned long long s_chg[2];
-    const int64_t q = blockIdx.x;
-    if (q >= A.nq) return;
     const int lane = lane_id();
     TTGeo g;
     tt_setup(A, q, g);
@@ -611,66 +609,99 @@ __global__ void __launch_bounds__(64) k_tt_solve(TTArgs A)
     const unsigned long long b_lo = __ballot(chg_lo), b_hi = __ballot(chg_hi);
     const int n_lo = __popcll(b_lo), n_hi = __popcll(b_hi);
     const int nv = n_lo + n_hi;
-    // ---- bisection: lane k takes the k-th sign-change piece
+    // ---- refine every sign-change piece to 1/1024 of its width.  The paper's
+    // 10 bisection steps evaluate 10 of the 1023 dyadic points of the piece; a
+    // 32-way split followed by a 32-way split of the chosen sub-piece evaluates
+    // the same lattice in two wave-wide rounds and, for a piece with one sign
+    // change, ends on the same final interval.  Two pieces per round (one per
+    // half wave).
+    auto sign_at_grid = [&](int j) -> int {   // scan sign at v_j (wave-uniform j)
+        const int lo = __shfl(s_lo, j & (kWave - 1), kWave);
+        const int hi = __shfl(s_hi, j & (kWave - 1), kWave);
+        return j < kWave ? lo : hi;
+    };
+    auto kth_piece = [&](int k) -> int {
+        unsigned long long m = k < n_lo ? b_lo : b_hi;
+        int r = k < n_lo ? k : k - n_lo;
+        for (int i = 0; i < r; ++i) m &= m - 1ull;
+        return __ffsll((long long)m) - 1 + (k < n_lo ? 0 : kWave);
+    };
+    const int nsplit = 1 << ((A.bisect_iters + 1) / 2);           // 32 for 10 steps
+    const int nsplit2 = 1 << (A.bisect_iters / 2);                // 32 for 10 steps
+    double my_v = 0.0;                                             // lane k keeps v of piece k
+    const int nvk = nv < kWave ? nv : kWave;
+    for (int base = 0; base < nvk; base += 2) {
+        const int h = lane >> 5, j = lane & 31;
+        const int k = base + h;
+        const bool act = k < nvk;
+        const int piece = act ? kth_piece(k) : 0;
+        // endpoint signs come from the scan; every lane evaluates its own grid index
+        const int pa = __shfl(piece, 0, kWave), pb = __shfl(piece, 32, kWave);
+        const int sla = sign_at_grid(pa), slb = sign_at_grid(pb);
+        int sl = h ? slb : sla;
+        double l = double(piece) / P, r = double(piece + 1) / P;
+        for (int round = 0; round < 2; ++round) {
+            const int ns = round == 0 ? nsplit : nsplit2;
+            int sj = sl;
+            if (act && j >= 1 && j < ns) sj = tt_det_sign(g, a.c, da, ma, l + (r - l) * double(j) / ns);
+            const int sprev = __shfl_up(sj, 1, kWave);
+            const bool chg = act && j >= 1 && j < ns && sj != (j == 1 ? sl : sprev);
+            const unsigned long long bal = __ballot(chg);
+            const unsigned int half = (unsigned int)(h ? (bal >> 32) : (bal & 0xffffffffull));
+            const int first = half ? __ffs(half) - 1 : ns;           // change between points first-1 and first
+            const int i = first - 1;                                 // sub-piece index
+            const int s_i = __shfl(sj, (h << 5) + (i > 0 ? i : 0), kWave);
+            const double nl = l + (r - l) * double(i) / ns, nr = l + (r - l) * double(i + 1) / ns;
+            sl = i == 0 ? sl : s_i;
+            l = nl;
+            r = nr;
+        }
+        const double v = 0.5 * (l + r);
+        // hand v to lane k
+        const double va = __shfl(v, 0, kWave), vb = __shfl(v, 32, kWave);
+        if (lane == base) my_v = va;
+        if (lane == base + 1 && base + 1 < nvk) my_v = vb;
+    }
+    // ---- path phase: lane k handles the v root of piece k
     LaneTT S;
     S.n = 0;
     int ncand = 0;
-    for (int base = 0; base < nv; base += kWave) {
-        const int k = base + lane;
-        bool mine = k < nv;
-        int piece = 0;
-        if (mine) {
-            // k-th set bit over the concatenated masks
-            unsigned long long m = k < n_lo ? b_lo : b_hi;
-            int r = k < n_lo ? k : k - n_lo;
-            for (int i = 0; i < r; ++i) m &= m - 1ull;
-            piece = __ffsll((long long)m) - 1 + (k < n_lo ? 0 : kWave);
-        }
-        if (mine) {
-            double l = double(piece) / P, r = double(piece + 1) / P;
-            int sl = tt_det_sign(g, a.c, da, ma, l);
-            for (int it = 0; it < A.bisect_iters; ++it) {
-                double m = 0.5 * (l + r);
-                if (tt_det_sign(g, a.c, da, ma, m) == sl) l = m;
-                else r = m;
-            }
-            const double v = 0.5 * (l + r);
-            // path phase: u from a(u)|_v on [-m, 1 - v + m]
-            double c[kDA + 1];
-            tt_acoef(a.c, da, ma, v, c);
-            double ur[kDA + 1];
-            bool uok[kDA + 1];
-            iso_level<kDA, kDA>(c, -A.u_margin, 1.0 - v + A.u_margin, ur, uok);
+    if (lane < nvk) {
+        const double v = my_v;
+        double c[kDA + 1];
+        tt_acoef(a.c, da, ma, v, c);
+        double ur[kDA + 1];
+        bool uok[kDA + 1];
+        iso_level<kDA, kDA>(c, -A.u_margin, 1.0 - v + A.u_margin, ur, uok);
 #pragma unroll 1
-            for (int t = 0; t <= kDA; ++t) {
-                if (!uok[t]) continue;
-                double u = ur[t], vv = v;
-                ncand++;
-                if (!tt_polish(g, A.polish_iters, u, vv)) continue;
-                if (!(u >= 0.0 && vv >= 0.0 && u + vv <= 1.0)) continue;
-                double u2, v2;
-                V3<double> x1, x2;
-                if (!tt_trace(g, u, vv, u2, v2, x1, x2)) continue;
-                if (!(u2 >= 0.0 && v2 >= 0.0 && u2 + v2 <= 1.0)) continue;
-                double r1, r2;
-                if (!law(g.x0, x1, x2, g.n10 + g.dn11 * u + g.dn12 * vv, g.eta0, g.eta1, r1)) continue;
-                if (!law(x1, x2, g.x3, g.n20 + g.dn21 * u2 + g.dn22 * v2, g.eta1, g.eta2, r2)) continue;
-                const double res = fmax(r1, r2);
-                if (!(res <= A.tau)) continue;
-                const double e1 = fmin(fmin(u, vv), 1.0 - u - vv), e2 = fmin(fmin(u2, v2), 1.0 - u2 - v2);
-                bool dup = false;
+        for (int t = 0; t <= kDA; ++t) {
+            if (!uok[t]) continue;
+            double u = ur[t], vv = v;
+            ncand++;
+            if (!tt_polish(g, A.polish_iters, u, vv)) continue;
+            if (!(u >= 0.0 && vv >= 0.0 && u + vv <= 1.0)) continue;
+            double u2, v2;
+            V3<double> x1, x2;
+            if (!tt_trace(g, u, vv, u2, v2, x1, x2)) continue;
+            if (!(u2 >= 0.0 && v2 >= 0.0 && u2 + v2 <= 1.0)) continue;
+            double r1, r2;
+            if (!law(g.x0, x1, x2, g.n10 + g.dn11 * u + g.dn12 * vv, g.eta0, g.eta1, r1)) continue;
+            if (!law(x1, x2, g.x3, g.n20 + g.dn21 * u2 + g.dn22 * v2, g.eta1, g.eta2, r2)) continue;
+            const double res = fmax(r1, r2);
+            if (!(res <= A.tau)) continue;
+            const double e1 = fmin(fmin(u, vv), 1.0 - u - vv), e2 = fmin(fmin(u2, v2), 1.0 - u2 - v2);
+            bool dup = false;
 #pragma unroll
-                for (int s = 0; s < kTTMaxSol; ++s)
-                    if (s < S.n && fabs(S.u1[s] - u) < A.dedup && fabs(S.v1[s] - vv) < A.dedup) dup = true;
-                if (dup || S.n >= kTTMaxSol) continue;
+            for (int q2 = 0; q2 < kTTMaxSol; ++q2)
+                if (q2 < S.n && fabs(S.u1[q2] - u) < A.dedup && fabs(S.v1[q2] - vv) < A.dedup) dup = true;
+            if (dup || S.n >= kTTMaxSol) continue;
 #pragma unroll
-                for (int s = 0; s < kTTMaxSol; ++s)
-                    if (s == S.n) {
-                        S.u1[s] = u; S.v1[s] = vv; S.u2[s] = u2; S.v2[s] = v2;
-                        S.res[s] = res; S.edge[s] = fmin(e1, e2);
-                    }
-                S.n++;
-            }
+            for (int q2 = 0; q2 < kTTMaxSol; ++q2)
+                if (q2 == S.n) {
+                    S.u1[q2] = u; S.v1[q2] = vv; S.u2[q2] = u2; S.v2[q2] = v2;
+                    S.res[q2] = res; S.edge[q2] = fmin(e1, e2);
+                }
+            S.n++;
         }
     }
     // ---- de-duplicate across lanes (two v roots polishing onto one path), then compact
@@ -704,7 +735,7 @@ __global__ void __launch_bounds__(64) k_tt_solve(TTArgs A)
             if (!((keepmask >> s) & 1)) continue;
             if (idx < (unsigned long long)A.cap) {
                 spoly_solution o;
-                o.query = int32_t(q);
+                o.query = int32_t(q + qid_offset);
                 o.tri[0] = A.q_tris[2 * q];
                 o.tri[1] = A.q_tris[2 * q + 1];
                 o.flags = 0;
@@ -731,7 +762,7 @@ __global__ void __launch_bounds__(64) k_tt_solve(TTArgs A)
     }
 }
 
-// ------------------------------------------------------------------ S0 for two vertices
+// ------------------------------------------------------------------ normal-cone cull for two vertices
 // Direction cone from a sphere (centre `from`, radius r) to a point or sphere at
 // `to`: unit axis a, chord bound ch = 2 sin(theta/2), theta = asin(r/|to-from|).
 __device__ __forceinline__ bool dir_cone_f(float3 from, float r, float3 to, float3& a, float& ch)
@@ -880,6 +911,14 @@ hipError_t launch_tt_cull(const CullTTArgs& A, int j3, int64_t n_pairs, hipStrea
     if (nb > 2147483647LL) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_tt_cull, dim3(unsigned(nb)), dim3(256), 0, stream, A, j3, n_pairs);
     return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(64) k_tt_solve(TTArgs A)
+{
+    __shared__ double lds[kLdsDoubles];
+    const int64_t q = blockIdx.x;
+    if (q >= A.nq) return;
+    tt_tuple(A, q, lds, 0);
 }
 
 hipError_t launch_tt_solve(const TTArgs& A, hipStream_t stream)

@@ -1,4 +1,4 @@
-"""Training, calibration and use of the learned two-vertex tuple pruner (S8).
+"""Training, calibration and use of the learned two-vertex tuple pruner.
 
 Labels come from the solver itself: a tuple is positive iff the exhaustive
 two-vertex solve (spoly_solve_nbounce) returns at least one admissible path

@@ -26,7 +26,8 @@ assert SOLUTION_DTYPE.itemsize == 56
 
 EXPORTED = ("spoly_ctx_create", "spoly_ctx_destroy", "spoly_default_params", "spoly_status_str",
             "spoly_cull_1bounce", "spoly_solve_1bounce", "spoly_cull_2bounce", "spoly_solve_nbounce",
-            "spoly_prune_score", "spoly_pruner_fwd_bwd", "spoly_pruner_step", "spoly_pruner_features")
+            "spoly_prune_score", "spoly_pruner_fwd_bwd", "spoly_pruner_step", "spoly_pruner_features",
+            "spoly_solve_mixed", "spoly_tt_default_params")
 PRUNER_NPARAMS = 38657
 
 
@@ -42,6 +43,11 @@ class Mesh(ctypes.Structure):
 
 class Points(ctypes.Structure):
     _fields_ = [("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p), ("n", ctypes.c_int32)]
+
+
+class MixedShape(ctypes.Structure):
+    _fields_ = [("workgroups_per_cu", ctypes.c_int32), ("r_tile", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
 
 
 class Params(ctypes.Structure):
@@ -68,6 +74,8 @@ def load_library(path: str = LIB_PATH):
     L.spoly_ctx_destroy.restype = None
     L.spoly_default_params.argtypes = [ctypes.POINTER(Params)]
     L.spoly_default_params.restype = None
+    L.spoly_tt_default_params.argtypes = [ctypes.POINTER(Params)]
+    L.spoly_tt_default_params.restype = None
     L.spoly_status_str.argtypes = [ctypes.c_int]
     L.spoly_status_str.restype = ctypes.c_char_p
     L.spoly_cull_1bounce.argtypes = [P, ctypes.POINTER(Mesh), ctypes.POINTER(Points), ctypes.POINTER(Points), D, D, D,
@@ -93,6 +101,9 @@ def load_library(path: str = LIB_PATH):
     L.spoly_pruner_step.restype = ctypes.c_int
     L.spoly_pruner_features.argtypes = [P, MP, PP, PP, P, P, P, I64, P, P]
     L.spoly_pruner_features.restype = ctypes.c_int
+    L.spoly_solve_mixed.argtypes = [P, MP, PP, PP, P, P, P, I64, ctypes.c_int, D, D, MP, PP, PP, P, P, P, I64, P,
+                                    ctypes.c_int, ctypes.POINTER(Params), ctypes.POINTER(MixedShape), P, P, I64, P, P]
+    L.spoly_solve_mixed.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -106,6 +117,12 @@ def _check(st: int, what: str):
 def default_params() -> Params:
     p = Params()
     load_library().spoly_default_params(ctypes.byref(p))
+    return p
+
+
+def tt_default_params() -> Params:
+    p = Params()
+    load_library().spoly_tt_default_params(ctypes.byref(p))
     return p
 
 
@@ -161,7 +178,7 @@ class Context:
         except Exception:
             pass
 
-    # ---------------------------------------------------------------- S0
+    # ---------------------------------------------------------------- normal-cone cull
     def cull_1bounce(self, mesh: DeviceMesh, x0s: DevicePoints, x2s: DevicePoints, eta0=1.0, eta1=1.0,
                      margin=1e-3, capacity: int | None = None):
         """Returns int32 device tensors (q_x0, q_x2, q_tri) of the kept triples."""
@@ -181,7 +198,7 @@ class Context:
                 return qx0[:n], qx2[:n], qt[:n]
             cap = n
 
-    # ---------------------------------------------------------------- S1-S7
+    # ---------------------------------------------------------------- solve
     def solve_1bounce(self, mesh: DeviceMesh, x0s: DevicePoints, x2s: DevicePoints, q_x0: torch.Tensor,
                       q_x2: torch.Tensor, q_tri: torch.Tensor, event: str, eta0=1.0, eta1=1.0,
                       precision: int = SPOLY_FP64, params: Params | None = None, capacity: int | None = None,
@@ -250,7 +267,7 @@ def _solve_2bounce(self, mesh: DeviceMesh, x0s: DevicePoints, x3s: DevicePoints,
     """TT chain x0 -> T1 -> T2 -> x3 (refraction at both vertices)."""
     L = load_library()
     nq = int(q_x0.numel())
-    prm = params or default_params()
+    prm = params or tt_default_params()
     chain = (ctypes.c_int * 2)(SPOLY_T, SPOLY_T)
     e = _host_doubles(eta)
     tb = _host_doubles(sqrt_table) if sqrt_table is not None else None
@@ -310,6 +327,44 @@ def _prune_score(self, mesh, x0s, x3s, q_x0, q_x3, q_tris, params, threshold, sc
     return kp, kc
 
 
+def _solve_mixed(self, mesh1, x0s1, x2s1, q1_x0, q1_x2, q1_tri, event, eta0, eta1, mesh2, x0s2, x3s2, q2_x0,
+                 q2_x3, q2_tris, eta2=(1.0, 1.5, 1.0), precision=SPOLY_FP32_POLISH64, params=None, shape=None,
+                 out=None, out_count=None, queue=None, sync=True, capacity=None):
+    """One persistent launch over both problems; queries of problem 2 are offset
+    by the number of problem-1 queries.  With sync=False the caller owns (and
+    zeroes) `queue` and `out_count`, e.g. inside a captured graph."""
+    L = load_library()
+    n1, n2 = int(q1_tri.numel()), int(q2_x0.numel())
+    prm = params or default_params()
+    shp = shape or MixedShape(2, 256, 0, 0)
+    e2 = _host_doubles(eta2)
+    ev = SPOLY_T if event == "T" else SPOLY_R
+    cap = capacity if capacity is not None else max(1024, (n1 + n2) // 4)
+    while True:
+        buf = out if out is not None else torch.empty(cap * SOLUTION_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+        cnt = out_count if out_count is not None else torch.zeros(1, dtype=torch.int64, device="cuda")
+        qq = queue if queue is not None else torch.zeros(1, dtype=torch.int64, device="cuda")
+        if sync:
+            cnt.zero_()
+            qq.zero_()
+        _check(L.spoly_solve_mixed(self.h, ctypes.byref(mesh1.c), ctypes.byref(x0s1.c), ctypes.byref(x2s1.c),
+                                   _ptr(q1_x0), _ptr(q1_x2), _ptr(q1_tri), n1, ev, eta0, eta1, ctypes.byref(mesh2.c),
+                                   ctypes.byref(x0s2.c), ctypes.byref(x3s2.c), _ptr(q2_x0), _ptr(q2_x3),
+                                   _ptr(q2_tris), n2, e2, precision, ctypes.byref(prm), ctypes.byref(shp), _ptr(qq),
+                                   _ptr(buf), buf.numel() // SOLUTION_DTYPE.itemsize, _ptr(cnt), _stream()),
+               "spoly_solve_mixed", "spoly_tt_default_params")
+        if not sync:
+            return buf, cnt
+        n = int(cnt.item())
+        capn = buf.numel() // SOLUTION_DTYPE.itemsize
+        if n <= capn:
+            return buf[: n * SOLUTION_DTYPE.itemsize].cpu().numpy().view(SOLUTION_DTYPE)
+        if out is not None:
+            raise SpolyError(f"output capacity {capn} < {n} solutions")
+        cap = n
+
+
+Context.solve_mixed = _solve_mixed
 Context.pruner_features = _pruner_features
 Context.pruner_fwd_bwd = _pruner_fwd_bwd
 Context.pruner_step = _pruner_step

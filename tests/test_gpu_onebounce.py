@@ -1,4 +1,4 @@
-"""GPU parity of the one-vertex path (S0-S7) against the FP64 oracle, through the C ABI."""
+"""GPU parity of the one-vertex path (cull and solve) against the FP64 oracle, through the C ABI."""
 import numpy as np
 import pytest
 import torch
