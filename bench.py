@@ -113,7 +113,20 @@ def main():
     ap.add_argument("--res", type=int, default=256, help="shading points per side")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--legs", default="glints,mixed,caustic",
+                    help="comma list: glints (the headline line), mixed (2M-instance persistent launch), "
+                         "caustic (learned pruner against the exhaustive two-vertex solve)")
+    ap.add_argument("--mixed-total", type=int, default=2_000_000)
+    ap.add_argument("--caustic-stride", type=int, default=16, help="every k-th receiver of the 64x64 grid")
+    ap.add_argument("--pruner", default=None, help="trained pruner .npz (default: the packaged weights)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device-to-device copy 5 times (the reference kernel for scaling "
+                         "FETCH_SIZE / WRITE_SIZE counters) and exit")
     args = ap.parse_args()
+    legs = set(args.legs.split(","))
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
               "(instances are independent; see the sharding notes in the design document).", file=sys.stderr)
@@ -242,10 +255,121 @@ def main():
             "peak_note": "fp32/fp64 vector FMA without packed fp32 (packed-fp32 peak 157.3)",
         },
     }
+    if "mixed" in legs:
+        out["mixed"] = mixed_leg(args, ctx)
+    if "caustic" in legs:
+        out["pruned_vs_exhaustive"] = caustic_leg(args, ctx)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args, mesh, light)
     print(json.dumps(out), flush=True)
     ctx.close()
+
+
+def copy_calibration(nbytes: int = 256 << 20, reps: int = 5):
+    """A plain copy of known size: each launch reads and writes nbytes."""
+    import torch
+
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps}), flush=True)
+
+
+def mixed_leg(args, ctx):
+    """2M instances, 70% drawn from the 32768 one-vertex reflection instances of
+    the 16x16 heightfield scene and 30% from the canonical cone-culled TT
+    tuples of the 64x64-receiver caustic scene, in one persistent launch
+    captured in a graph, with the autotuned shape.  FP32 bulk, FP64 polish."""
+    import torch
+    from paper_2405_13409_amd import autotune, caustic, scenes, spoly
+
+    w = scenes.glints_small()
+    m1 = spoly.DeviceMesh(w.mesh.P, w.mesh.N, w.mesh.tri)
+    p1 = (spoly.DevicePoints(w.x0), spoly.DevicePoints(w.x2))
+    sph = scenes.caustic_sphere()
+    m2 = spoly.DeviceMesh(sph.P, sph.N, sph.tri)
+    r2 = spoly.DevicePoints(scenes.caustic_receivers())
+    l2 = spoly.DevicePoints(scenes.CAUSTIC_LIGHT_OUTSIDE)
+    T = caustic.cull_sorted(ctx, m2, r2, l2)
+    i1, i2 = scenes.mixed_draw(len(w.q_tri), T.n, args.mixed_total, 0.7, 4)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).cuda()  # noqa: E731
+    q1 = (dev(w.q_x0[i1]), dev(w.q_x2[i1]), dev(w.q_tri[i1]))
+    Q2 = T.take(torch.from_numpy(i2).cuda())
+    n_tt_list = T.n
+    del T
+    cap = 1 << 20
+    out = torch.empty(cap * spoly.SOLUTION_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    queue = torch.zeros(1, dtype=torch.int64, device="cuda")
+    prec = spoly.SPOLY_FP32_POLISH64
+
+    def launch(shape):
+        cnt.zero_()
+        queue.zero_()
+        ctx.solve_mixed(m1, *p1, *q1, "R", 1.0, 1.0, m2, r2, l2, Q2.q0, Q2.q3, Q2.qt, precision=prec, shape=shape,
+                        out=out, out_count=cnt, queue=queue, sync=False)
+
+    cand = {"workgroups_per_cu": (1, 2, 4), "r_tile": (256, 1024), "order": (0, 2)}
+    key = autotune.signature(len(i1), len(i2), "R", prec)
+    best, timings, cached = autotune.tune(launch, key, reps=1, candidates=cand)
+    print(f"[bench] mixed autotune best {best.workgroups_per_cu}/{best.r_tile}/{best.order} "
+          f"(cached={cached})", file=sys.stderr, flush=True)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        launch(best)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        launch(best)
+    ms, counts = [], []
+    for _ in range(3):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        g.replay()
+        b.record()
+        b.synchronize()
+        ms.append(a.elapsed_time(b))
+        counts.append(int(cnt.item()))
+    assert counts[0] <= cap and len(set(counts)) == 1, counts
+    med = float(np.median(ms))
+    return {"workload": f"{len(i1)} one-vertex R (16x16 heightfield, 64 points) + {len(i2)} TT tuples drawn from "
+                        f"{n_tt_list} culled tuples of the 64x64 caustic grid, seed 4",
+            "instances": len(i1) + len(i2), "ms": med, "instances_per_s": (len(i1) + len(i2)) / med * 1e3,
+            "valid_paths": counts[0], "valid_paths_per_s": counts[0] / med * 1e3,
+            "shape": {"workgroups_per_cu": best.workgroups_per_cu, "r_tile": best.r_tile, "order": best.order},
+            "autotune_ms": timings, "graph": True, "precision": "fp32 bulk, fp64 polish (TT fp64)"}
+
+
+def caustic_leg(args, ctx):
+    """Learned pruner against the exhaustive two-vertex solve on a subset of
+    the 64x64 receiver grid (every --caustic-stride-th receiver)."""
+    from paper_2405_13409_amd import caustic, scenes, spoly, train_pruner
+
+    path = args.pruner or train_pruner.DEFAULT_OUT
+    if not os.path.exists(path):
+        return {"skipped": f"no trained pruner at {os.path.relpath(path, ROOT)}"}
+    net = train_pruner.load(path)
+    sph = scenes.caustic_sphere()
+    dm = spoly.DeviceMesh(sph.P, sph.N, sph.tri)
+    rec = scenes.caustic_receivers()[:: args.caustic_stride]
+    d0 = spoly.DevicePoints(rec)
+    dl = spoly.DevicePoints(scenes.CAUSTIC_LIGHT_OUTSIDE)
+    T = caustic.cull_sorted(ctx, dm, d0, dl)
+    r = caustic.prune_vs_exhaustive(ctx, dm, d0, dl, T, net, reps=3).as_dict()
+    r["exhaustive_solves_per_s"] = r["n_tuples"] / r["ms_exhaustive"] * 1e3
+    r["pruned_solves_per_s"] = r["n_tuples"] / r["ms_pruned"] * 1e3
+    r["exhaustive_paths_per_s"] = r["paths_exhaustive"] / r["ms_exhaustive"] * 1e3
+    r["pruned_paths_per_s"] = r["paths_pruned"] / r["ms_pruned"] * 1e3
+    r["workload"] = (f"{len(rec)} receivers (64x64 grid on [-2,2]^2 at z=-1, stride {args.caustic_stride}), "
+                     f"icosphere 1280 tris IOR 1.5, light (0.1,0.05,1.5); TT chain")
+    r["threshold"] = net.threshold
+    r["train"] = train_pruner.load_meta(path)
+    return r
 
 
 def cpu_baseline(args, mesh, light):

@@ -39,34 +39,58 @@ __global__ void __launch_bounds__(256) k_tri_cones(const double* px, const doubl
 
 constexpr int kCullPts = 64;  // (x0, x2) pairs per thread; one atomic per wave per 64 pairs
 
-__device__ __forceinline__ bool cone_keep(float4 c0, float4 c1, float px, float py, float pz, float qx, float qy,
-                                          float qz, float eta0, float eta1, float margin)
+// One side of the half-vector bound: the unit direction from the triangle's
+// bounding sphere (centre c, radius rad) towards point p, scaled by eta, and
+// eta times the chord 2 sin(theta/2) of the direction cone's half angle
+// theta = asin(rad / |p - c|).  Returns false when p lies inside the sphere
+// (the direction is then unbounded).
+struct ConeSide {
+    float hx, hy, hz, dch;
+};
+
+__device__ __forceinline__ bool cone_side(float4 c0, float px, float py, float pz, float eta, ConeSide& s)
 {
-    float ax = px - c0.x, ay = py - c0.y, az = pz - c0.z;
-    float bx = qx - c0.x, by = qy - c0.y, bz = qz - c0.z;
-    float da = sqrtf(ax * ax + ay * ay + az * az), db = sqrtf(bx * bx + by * by + bz * bz);
-    const float rad = c0.w;
-    if (!(da > rad * 1.0001f) || !(db > rad * 1.0001f) || !(c1.w < 1.5707f)) return true;
-    float ia = 1.0f / da, ib = 1.0f / db;
-    ax *= ia; ay *= ia; az *= ia;
-    bx *= ib; by *= ib; bz *= ib;
-    float sa = rad * ia, sb = rad * ib;
-    float chord_a = sqrtf(fmaxf(0.0f, 2.0f - 2.0f * sqrtf(fmaxf(0.0f, 1.0f - sa * sa))));
-    float chord_b = sqrtf(fmaxf(0.0f, 2.0f - 2.0f * sqrtf(fmaxf(0.0f, 1.0f - sb * sb))));
-    float hx = eta0 * ax + eta1 * bx, hy = eta0 * ay + eta1 * by, hz = eta0 * az + eta1 * bz;
-    float L = sqrtf(hx * hx + hy * hy + hz * hz);
-    float delta = (eta0 * chord_a + eta1 * chord_b) * 1.0001f + 1e-6f;
-    if (!(delta < L)) return true;
-    float lim = c1.w + asinf(fminf(1.0f, delta / L)) + margin;
-    if (lim >= 1.5707f) return true;
-    float cphi = fabsf(c1.x * hx + c1.y * hy + c1.z * hz) / L;
-    return cphi >= cosf(lim) * (1.0f - 1e-6f);
+    const float ax = px - c0.x, ay = py - c0.y, az = pz - c0.z;
+    const float d2 = ax * ax + ay * ay + az * az;
+    const float rl = c0.w * 1.0001f;
+    if (!(d2 > rl * rl)) return false;
+    const float ia = __builtin_amdgcn_rsqf(d2);
+    const float sa = c0.w * ia * 1.000001f;
+    const float co = __builtin_amdgcn_sqrtf(fmaxf(0.0f, 1.0f - sa * sa));   // cos theta
+    // 2 sin(theta/2) = sqrt(2 (1 - cos theta)) = sin theta sqrt(2 / (1 + cos theta)), free of cancellation
+    const float chord = sa * __builtin_amdgcn_rsqf(0.5f * (1.0f + co)) * 1.000001f;
+    const float e = eta * ia;
+    s.hx = e * ax;
+    s.hy = e * ay;
+    s.hz = e * az;
+    s.dch = eta * chord;
+    return true;
+}
+
+// Keep unless h = eta_a w_a + eta_b w_b (w in their direction cones) cannot be
+// parallel to any normal of the normal cone (axis an, half angle thn).  h lies
+// within asin(delta/L) of H = eta_a a_a + eta_b a_b, |H| = L, delta the sum of
+// the scaled chords; the test is angle(+-an, H) > thn + margin + asin(delta/L),
+// written with cosines: cth = cos(thn + margin), sth = sin(thn + margin).
+__device__ __forceinline__ bool cone_meet(float4 c1, float cth, float sth, const ConeSide& a, const ConeSide& b)
+{
+    const float hx = a.hx + b.hx, hy = a.hy + b.hy, hz = a.hz + b.hz;
+    const float iL = __builtin_amdgcn_rsqf(hx * hx + hy * hy + hz * hz);
+    const float delta = (a.dch + b.dch) * 1.0001f + 1e-6f;
+    const float sphi = delta * iL * 1.000001f;
+    if (!(sphi < 1.0f)) return true;
+    const float cphi = __builtin_amdgcn_sqrtf(1.0f - sphi * sphi);
+    const float clim = cth * cphi - sth * sphi;            // cos(thn + margin + phi)
+    if (!(clim > 1e-4f)) return true;                      // the cones reach 90 degrees
+    const float cdot = fabsf(c1.x * hx + c1.y * hy + c1.z * hz) * iL;
+    return cdot >= clim * (1.0f - 4e-6f);
 }
 
 // Grid: (pair block) x (triangle block of 256).  Each thread tests one
 // triangle against kCullPts consecutive (x0, x2) pairs, keeping the wave's
 // per-pair ballots in LDS; the wave then reserves its whole output range with
-// one atomic and writes the kept triples pair by pair (coalesced).
+// one atomic and writes the kept triples pair by pair (coalesced).  The x2
+// side of the bound is recomputed only when x2 changes (with one light: once).
 __global__ void __launch_bounds__(256) k_cull_1bounce(CullArgs A)
 {
     __shared__ unsigned long long s_bal[4][kCullPts];
@@ -81,18 +105,36 @@ __global__ void __launch_bounds__(256) k_cull_1bounce(CullArgs A)
         c0 = A.tri_cone[2 * t];
         c1 = A.tri_cone[2 * t + 1];
     }
+    // a normal cone of 90 degrees or more (with the margin) meets every h
+    const float thm = c1.w + A.margin;
+    const bool all = !(thm < 1.5707f);
+    const float cth = cosf(fminf(thm, 1.5707f)), sth = sinf(fminf(thm, 1.5707f));
     const int64_t n_pairs = int64_t(A.n0) * A.n2;
     const int64_t pair0 = pblock * kCullPts;
     const int npairs = int(min<int64_t>(kCullPts, n_pairs - pair0));
+    int j0 = int(pair0 / A.n2), j2 = int(pair0 % A.n2);
+    int j2_side = -1;
+    ConeSide sb{0.0f, 0.0f, 0.0f, 0.0f};
+    bool b_ok = false;
     int mine = 0;
     for (int k = 0; k < npairs; ++k) {
-        const int64_t pr = pair0 + k;
-        const int j0 = int(pr / A.n2), j2 = int(pr % A.n2);
-        bool keep = tri_ok && cone_keep(c0, c1, float(A.x0x[j0]), float(A.x0y[j0]), float(A.x0z[j0]), float(A.x2x[j2]),
-                                        float(A.x2y[j2]), float(A.x2z[j2]), A.eta0, A.eta1, A.margin);
+        bool keep = false;
+        if (tri_ok) {
+            if (j2 != j2_side) {
+                b_ok = cone_side(c0, float(A.x2x[j2]), float(A.x2y[j2]), float(A.x2z[j2]), A.eta1, sb);
+                j2_side = j2;
+            }
+            ConeSide sa;
+            const bool a_ok = cone_side(c0, float(A.x0x[j0]), float(A.x0y[j0]), float(A.x0z[j0]), A.eta0, sa);
+            keep = all || !a_ok || !b_ok || cone_meet(c1, cth, sth, sa, sb);
+        }
         const unsigned long long bal = __ballot(keep);
         if (lane == 0) s_bal[w][k] = bal;
         mine += keep ? 1 : 0;
+        if (++j2 == A.n2) {
+            j2 = 0;
+            ++j0;
+        }
     }
     const int incl = wave_incl_scan(mine);
     const int total = __shfl(incl, kWave - 1, kWave);
@@ -104,18 +146,22 @@ __global__ void __launch_bounds__(256) k_cull_1bounce(CullArgs A)
     __builtin_amdgcn_wave_barrier();
     unsigned long long off = base;
     const unsigned long long lt = (1ull << lane) - 1ull;
+    int o0 = int(pair0 / A.n2), o2 = int(pair0 % A.n2);
     for (int k = 0; k < npairs; ++k) {
         const unsigned long long bal = s_bal[w][k];
         if ((bal >> lane) & 1ull) {
             const unsigned long long idx = off + (unsigned long long)__popcll(bal & lt);
             if (idx < (unsigned long long)A.cap) {
-                const int64_t pr = pair0 + k;
-                A.out_x0[idx] = int(pr / A.n2);
-                A.out_x2[idx] = int(pr % A.n2);
+                A.out_x0[idx] = o0;
+                A.out_x2[idx] = o2;
                 A.out_tri[idx] = t;
             }
         }
         off += (unsigned long long)__popcll(bal);
+        if (++o2 == A.n2) {
+            o2 = 0;
+            ++o0;
+        }
     }
 }
 

@@ -34,6 +34,7 @@ template <typename R, int EV>
 __global__ void __launch_bounds__(64) k_mixed(MixedArgs M)
 {
     __shared__ double lds[kLdsDoubles];
+    __shared__ TTGeo sgeo;
     const int lane = lane_id();
     for (;;) {
         unsigned long long item = 0;
@@ -52,7 +53,7 @@ __global__ void __launch_bounds__(64) k_mixed(MixedArgs M)
                 onebounce_lane<R, EV>(M.r, q, q < b1, 0);
             }
         } else {
-            tt_tuple(M.t, idx, lds, M.r.nq);
+            tt_tuple(M.t, idx, lds, &sgeo, M.r.nq);
         }
         __syncthreads();
     }

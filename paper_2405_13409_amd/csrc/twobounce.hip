@@ -346,25 +346,28 @@ __host__ __device__ constexpr double binom(int n, int k)
     return r;
 }
 
-template <int d>
-__device__ __forceinline__ void horner2(const double (&q)[d + 1], double x, double& f, double& fp)
+// f and f' of the level polynomial q_k = c[k+m] C(k+m, m), k = 0..d (the m-th
+// derivative of sum c_k x^k divided by m!), read straight from c.
+template <int DMAX, int d>
+__device__ __forceinline__ void horner_lv(const double (&c)[DMAX + 1], double x, double& f, double& fp)
 {
-    f = q[d];
+    constexpr int m = DMAX - d;
+    f = c[d + m] * binom(d + m, m);
     fp = 0.0;
 #pragma unroll
     for (int k = d - 1; k >= 0; --k) {
         fp = fma(fp, x, f);
-        f = fma(f, x, q[k]);
+        f = fma(f, x, c[k + m] * binom(k + m, m));
     }
 }
 
-template <int d>
-__device__ __forceinline__ double refine(const double (&q)[d + 1], double l, double r, bool neg_l)
+template <int DMAX, int d>
+__device__ __forceinline__ double refine(const double (&c)[DMAX + 1], double l, double r, bool neg_l)
 {
     double x = 0.5 * (l + r);
     for (int it = 0; it < 100; ++it) {
         double f, fp;
-        horner2<d>(q, x, f, fp);
+        horner_lv<DMAX, d>(c, x, f, fp);
         if (f == 0.0) return x;
         if ((f < 0.0) == neg_l) l = x;
         else r = x;
@@ -377,48 +380,64 @@ __device__ __forceinline__ double refine(const double (&q)[d + 1], double l, dou
     return x;
 }
 
+// Level d of the recursion: rt[k] for the slots k set in the returned mask.
+// The piece ends are the roots of level d-1 (bit mask `bmask`, values bp).
 template <int DMAX, int d>
-__device__ __forceinline__ void iso_level(const double (&c)[DMAX + 1], double lo, double hi, double (&rt)[DMAX + 1],
-                                          bool (&ok)[DMAX + 1])
+__device__ __forceinline__ unsigned iso_level(const double (&c)[DMAX + 1], double lo, double hi,
+                                              double (&rt)[DMAX + 1])
 {
     double bp[DMAX + 1];
-    bool bok[DMAX + 1];
-    if constexpr (d == 1) {
+    unsigned bmask = 0u;
+    if constexpr (d > 1) bmask = iso_level<DMAX, d - 1>(c, lo, hi, bp);
+    // pass 1: bit k set if piece k (ending at bp[k], or at hi for k = d) has a strict sign change
+    unsigned mask = 0u;
+    {
+        double l = lo, f_lo, dummy;
+        horner_lv<DMAX, d>(c, lo, f_lo, dummy);
 #pragma unroll
-        for (int k = 0; k <= DMAX; ++k) { bok[k] = false; bp[k] = 0.0; }
-    } else {
-        iso_level<DMAX, d - 1>(c, lo, hi, bp, bok);
+        for (int k = 0; k <= d; ++k) {
+            const bool has = (k < d) ? ((bmask >> k) & 1u) != 0u : true;
+            const double r = (k < d) ? bp[k] : hi;
+            if (has) {
+                double f_r, dd;
+                horner_lv<DMAX, d>(c, r, f_r, dd);
+                if (r > l && ((f_lo < 0.0) != (f_r < 0.0))) mask |= 1u << k;
+                l = r;
+                f_lo = f_r;
+            }
+        }
     }
-    constexpr int m = DMAX - d;
-    double q[d + 1];
+    // pass 2: one refinement per sign-change piece of this lane
+    unsigned todo = mask;
+    while (todo) {
+        const int k = __builtin_ctz(todo);
+        todo &= todo - 1u;
+        double l = lo, r = hi;
 #pragma unroll
-    for (int k = 0; k <= d; ++k) q[k] = c[k + m] * binom(k + m, m);
-    double l = lo, f_lo, dummy;
-    horner2<d>(q, lo, f_lo, dummy);
+        for (int j = 0; j < d; ++j) {
+            if (((bmask >> j) & 1u) && j < k) l = bp[j];
+            if (j == k) r = bp[j];
+        }
+        double f_l, dd;
+        horner_lv<DMAX, d>(c, l, f_l, dd);
+        const double x = refine<DMAX, d>(c, l, r, f_l < 0.0);
+#pragma unroll
+        for (int j = 0; j <= d; ++j)
+            if (j == k) rt[j] = x;
+    }
+    // pass 3: slot order, near-duplicates dropped
+    unsigned okm = 0u;
     double last = -1e300;
 #pragma unroll
     for (int k = 0; k <= d; ++k) {
-        ok[k] = false;
-        rt[k] = 0.0;
-        const bool has = (k < d) ? bok[k] : true;
-        const double r = (k < d) ? bp[k] : hi;
-        if (has) {
-            double f_r, dd;
-            horner2<d>(q, r, f_r, dd);
-            if (r > l && ((f_lo < 0.0) != (f_r < 0.0))) {
-                double x = refine<d>(q, l, r, f_lo < 0.0);
-                if (x - last > 1e-12 * fmax(1.0, fabs(x))) {
-                    rt[k] = x;
-                    ok[k] = true;
-                    last = x;
-                }
+        if ((mask >> k) & 1u) {
+            if (rt[k] - last > 1e-12 * fmax(1.0, fabs(rt[k]))) {
+                okm |= 1u << k;
+                last = rt[k];
             }
-            l = r;
-            f_lo = f_r;
         }
     }
-#pragma unroll
-    for (int k = d + 1; k <= DMAX; ++k) { ok[k] = false; rt[k] = 0.0; }
+    return okm;
 }
 
 // ------------------------------------------------------------------ b(u,v) through its defining products
@@ -454,6 +473,22 @@ __device__ __forceinline__ void tt_acoef(const double* __restrict__ Ac, int da, 
     }
 }
 
+// An upper bound of x^(1/k) for x >= 0, within 0.2% of it: the exponent is
+// split off exactly (frexp) and only the logarithm of the mantissa and the
+// fractional power of two go through single-precision transcendentals.  The
+// bound only sizes the isolation interval, so a slightly larger value leaves
+// the roots found unchanged.
+__device__ __forceinline__ double root_k_upper(double x, int k)
+{
+    if (!(x > 0.0)) return 0.0;
+    if (!isfinite(x)) return x;
+    int e;
+    const double mnt = frexp(x, &e);                        // x = mnt 2^e, mnt in [1/2, 1)
+    const float t = (float(e) + log2f(float(mnt))) / float(k);
+    const float fl = floorf(t);
+    return ldexp(double(exp2f(t - fl)), int(fl)) * 1.002;
+}
+
 // sign of det R(v) (up to a constant sign): product of sgn b over the real roots of a(., v)
 __device__ int tt_det_sign(const TTGeo& g, const double* __restrict__ Ac, int da, int ma, double v)
 {
@@ -471,24 +506,28 @@ __device__ int tt_det_sign(const TTGeo& g, const double* __restrict__ Ac, int da
 #pragma unroll
         for (int i = 0; i <= kDA; ++i)
             if (i == ma - k) ck = c[i];
-        if (k <= ma) B = fmax(B, pow(fabs(ck / lead), 1.0 / k));
+        if (k <= ma) B = fmax(B, root_k_upper(fabs(ck / lead), k));
     }
     B = 2.0 * B;
     if (!(B > 0.0)) B = 1.0;
-    double w[kDA + 1];
     double pw = 1.0;
 #pragma unroll
     for (int k = 0; k <= kDA; ++k) {
-        w[k] = c[k] * pw;
+        c[k] *= pw;
         pw *= B;
     }
     double rt[kDA + 1];
-    bool ok[kDA + 1];
-    iso_level<kDA, kDA>(w, -1.0, 1.0, rt, ok);
+    unsigned okm = iso_level<kDA, kDA>(c, -1.0, 1.0, rt);
     int s = 1;
+    while (okm) {
+        const int k = __builtin_ctz(okm);
+        okm &= okm - 1u;
+        double x = 0.0;
 #pragma unroll
-    for (int k = 0; k <= kDA; ++k)
-        if (ok[k] && tt_b_eval(g, rt[k] * B, v) < 0.0) s = -s;
+        for (int j = 0; j <= kDA; ++j)
+            if (j == k) x = rt[j];
+        if (tt_b_eval(g, x * B, v) < 0.0) s = -s;
+    }
     return s;
 }
 
@@ -580,12 +619,20 @@ __device__ __forceinline__ bool law(V3<double> xp, V3<double> x, V3<double> xn, 
 
 // ------------------------------------------------------------------ the fused kernel
 // One tuple per wave (the whole wave must call it); `lds` holds kLdsDoubles
-// doubles private to the wave.  Output records carry query id q + qid_offset.
-__device__ __forceinline__ void tt_tuple(const TTArgs& A, int64_t q, double* lds, int64_t qid_offset)
+// doubles and `sgeo` one TTGeo, both in LDS and private to the wave.  The
+// tuple's geometry is the same for every lane, so it is kept in LDS rather
+// than replicated in vector registers.  Output records carry query id
+// q + qid_offset.
+__device__ __forceinline__ void tt_tuple(const TTArgs& A, int64_t q, double* lds, TTGeo* sgeo, int64_t qid_offset)
 {
     const int lane = lane_id();
-    TTGeo g;
-    tt_setup(A, q, g);
+    {
+        TTGeo gl;
+        tt_setup(A, q, gl);
+        if (lane == 0) *sgeo = gl;
+    }
+    sync_wave();
+    const TTGeo& g = *sgeo;
     LP a;
     const int da = tt_build_a(g, lds, a);
     const int ma = tt_udeg(a);
@@ -609,74 +656,38 @@ __device__ __forceinline__ void tt_tuple(const TTArgs& A, int64_t q, double* lds
     const unsigned long long b_lo = __ballot(chg_lo), b_hi = __ballot(chg_hi);
     const int n_lo = __popcll(b_lo), n_hi = __popcll(b_hi);
     const int nv = n_lo + n_hi;
-    // ---- refine every sign-change piece to 1/1024 of its width.  The paper's
-    // 10 bisection steps evaluate 10 of the 1023 dyadic points of the piece; a
-    // 32-way split followed by a 32-way split of the chosen sub-piece evaluates
-    // the same lattice in two wave-wide rounds and, for a piece with one sign
-    // change, ends on the same final interval.  Two pieces per round (one per
-    // half wave).
-    auto sign_at_grid = [&](int j) -> int {   // scan sign at v_j (wave-uniform j)
-        const int lo = __shfl(s_lo, j & (kWave - 1), kWave);
-        const int hi = __shfl(s_hi, j & (kWave - 1), kWave);
-        return j < kWave ? lo : hi;
-    };
-    auto kth_piece = [&](int k) -> int {
-        unsigned long long m = k < n_lo ? b_lo : b_hi;
-        int r = k < n_lo ? k : k - n_lo;
-        for (int i = 0; i < r; ++i) m &= m - 1ull;
-        return __ffsll((long long)m) - 1 + (k < n_lo ? 0 : kWave);
-    };
-    const int nsplit = 1 << ((A.bisect_iters + 1) / 2);           // 32 for 10 steps
-    const int nsplit2 = 1 << (A.bisect_iters / 2);                // 32 for 10 steps
-    double my_v = 0.0;                                             // lane k keeps v of piece k
-    const int nvk = nv < kWave ? nv : kWave;
-    for (int base = 0; base < nvk; base += 2) {
-        const int h = lane >> 5, j = lane & 31;
-        const int k = base + h;
-        const bool act = k < nvk;
-        const int piece = act ? kth_piece(k) : 0;
-        // endpoint signs come from the scan; every lane evaluates its own grid index
-        const int pa = __shfl(piece, 0, kWave), pb = __shfl(piece, 32, kWave);
-        const int sla = sign_at_grid(pa), slb = sign_at_grid(pb);
-        int sl = h ? slb : sla;
-        double l = double(piece) / P, r = double(piece + 1) / P;
-        for (int round = 0; round < 2; ++round) {
-            const int ns = round == 0 ? nsplit : nsplit2;
-            int sj = sl;
-            if (act && j >= 1 && j < ns) sj = tt_det_sign(g, a.c, da, ma, l + (r - l) * double(j) / ns);
-            const int sprev = __shfl_up(sj, 1, kWave);
-            const bool chg = act && j >= 1 && j < ns && sj != (j == 1 ? sl : sprev);
-            const unsigned long long bal = __ballot(chg);
-            const unsigned int half = (unsigned int)(h ? (bal >> 32) : (bal & 0xffffffffull));
-            const int first = half ? __ffs(half) - 1 : ns;           // change between points first-1 and first
-            const int i = first - 1;                                 // sub-piece index
-            const int s_i = __shfl(sj, (h << 5) + (i > 0 ? i : 0), kWave);
-            const double nl = l + (r - l) * double(i) / ns, nr = l + (r - l) * double(i + 1) / ns;
-            sl = i == 0 ? sl : s_i;
-            l = nl;
-            r = nr;
-        }
-        const double v = 0.5 * (l + r);
-        // hand v to lane k
-        const double va = __shfl(v, 0, kWave), vb = __shfl(v, 32, kWave);
-        if (lane == base) my_v = va;
-        if (lane == base + 1 && base + 1 < nvk) my_v = vb;
-    }
-    // ---- path phase: lane k handles the v root of piece k
+    // ---- bisection (Sec. 5.2), then the path phase: lane k takes the k-th
+    // sign-change piece, runs the bisection steps on it (the v estimate is the
+    // final midpoint), solves u from a(u)|v, polishes and validates.
     LaneTT S;
     S.n = 0;
     int ncand = 0;
-    if (lane < nvk) {
-        const double v = my_v;
+    for (int base = 0; base < nv; base += kWave) {
+        const int k = base + lane;
+        if (k >= nv) continue;
+        unsigned long long m = k < n_lo ? b_lo : b_hi;
+        const int r0 = k < n_lo ? k : k - n_lo;
+        for (int i = 0; i < r0; ++i) m &= m - 1ull;
+        const int piece = __ffsll((long long)m) - 1 + (k < n_lo ? 0 : kWave);
+        double l = double(piece) / P, r = double(piece + 1) / P;
+        const int sl = tt_det_sign(g, a.c, da, ma, l);
+        for (int it = 0; it < A.bisect_iters; ++it) {
+            const double mm = 0.5 * (l + r);
+            if (tt_det_sign(g, a.c, da, ma, mm) == sl) l = mm;
+            else r = mm;
+        }
+        const double v = 0.5 * (l + r);
         double c[kDA + 1];
         tt_acoef(a.c, da, ma, v, c);
         double ur[kDA + 1];
-        bool uok[kDA + 1];
-        iso_level<kDA, kDA>(c, -A.u_margin, 1.0 - v + A.u_margin, ur, uok);
-#pragma unroll 1
-        for (int t = 0; t <= kDA; ++t) {
-            if (!uok[t]) continue;
-            double u = ur[t], vv = v;
+        unsigned um = iso_level<kDA, kDA>(c, -A.u_margin, 1.0 - v + A.u_margin, ur);
+        while (um) {
+            const int t = __builtin_ctz(um);
+            um &= um - 1u;
+            double u = 0.0, vv = v;
+#pragma unroll
+            for (int j = 0; j <= kDA; ++j)
+                if (j == t) u = ur[j];
             ncand++;
             if (!tt_polish(g, A.polish_iters, u, vv)) continue;
             if (!(u >= 0.0 && vv >= 0.0 && u + vv <= 1.0)) continue;
@@ -916,9 +927,10 @@ hipError_t launch_tt_cull(const CullTTArgs& A, int j3, int64_t n_pairs, hipStrea
 __global__ void __launch_bounds__(64) k_tt_solve(TTArgs A)
 {
     __shared__ double lds[kLdsDoubles];
+    __shared__ TTGeo sgeo;
     const int64_t q = blockIdx.x;
     if (q >= A.nq) return;
-    tt_tuple(A, q, lds, 0);
+    tt_tuple(A, q, lds, &sgeo, 0);
 }
 
 hipError_t launch_tt_solve(const TTArgs& A, hipStream_t stream)

@@ -216,3 +216,20 @@ def subsample(n_total: int, n_take: int, seed: int) -> np.ndarray:
     if n_take >= n_total:
         return np.arange(n_total, dtype=np.int64)
     return np.sort(rng.choice(n_total, n_take, replace=False)).astype(np.int64)
+
+
+def pruner_receivers(n: int, seed: int = 5) -> np.ndarray:
+    """Training receivers of the learned tuple pruner: x0 ~ U([-2,2]^2) at z = -1."""
+    return points_uniform(n, -2.0, 2.0, -1.0, seed)
+
+
+def mixed_draw(n_list_1: int, n_list_2: int, n_total: int = 2_000_000, frac_1: float = 0.7, seed: int = 4):
+    """Mixed batch: round(frac_1 * n_total) instances drawn with replacement
+    from a list of n_list_1 one-vertex instances, the rest from a list of
+    n_list_2 two-vertex tuples.  Returns the two index arrays (int64), each in
+    draw order."""
+    rng = np.random.default_rng(seed)
+    n1 = int(round(frac_1 * n_total))
+    i1 = rng.integers(0, n_list_1, n1) if n_list_1 > 0 else np.zeros(0, dtype=np.int64)
+    i2 = rng.integers(0, n_list_2, n_total - n1) if n_list_2 > 0 else np.zeros(0, dtype=np.int64)
+    return i1.astype(np.int64), i2.astype(np.int64)

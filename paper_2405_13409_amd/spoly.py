@@ -352,7 +352,7 @@ def _solve_mixed(self, mesh1, x0s1, x2s1, q1_x0, q1_x2, q1_tri, event, eta0, eta
                                    ctypes.byref(x0s2.c), ctypes.byref(x3s2.c), _ptr(q2_x0), _ptr(q2_x3),
                                    _ptr(q2_tris), n2, e2, precision, ctypes.byref(prm), ctypes.byref(shp), _ptr(qq),
                                    _ptr(buf), buf.numel() // SOLUTION_DTYPE.itemsize, _ptr(cnt), _stream()),
-               "spoly_solve_mixed", "spoly_tt_default_params")
+               "spoly_solve_mixed")
         if not sync:
             return buf, cnt
         n = int(cnt.item())

@@ -126,3 +126,76 @@ def test_autotuner_picks_and_caches(sp, problem, tmp_path):
     best2, _, cached2 = autotune.tune(run, "test", path, reps=1, candidates=cand)
     assert cached2 and (best2.workgroups_per_cu, best2.r_tile, best2.order) == (best.workgroups_per_cu, best.r_tile,
                                                                                  best.order)
+
+
+def test_mixed_2m_instances_graph_vs_separate_and_oracle(sp):
+    """2M instances (70% one-vertex R from the 16x16 heightfield scene, 30% TT
+    tuples drawn from the canonical culled list of the 64x64 caustic grid) in
+    one captured persistent launch: identical to the separate solves, and the
+    one-vertex part within the FP32-path tolerance of the FP64 oracle on a
+    seeded sample of instances."""
+    print("[gpu-case] mixed 2M", flush=True)
+    import oracle
+    import parity
+    from paper_2405_13409_amd import caustic
+
+    ctx = sp.Context(0)
+    w = scenes.glints_small()
+    m1 = sp.DeviceMesh(w.mesh.P, w.mesh.N, w.mesh.tri)
+    p1 = (sp.DevicePoints(w.x0), sp.DevicePoints(w.x2))
+    sph = scenes.caustic_sphere()
+    m2 = sp.DeviceMesh(sph.P, sph.N, sph.tri)
+    r2 = sp.DevicePoints(scenes.caustic_receivers())
+    l2 = sp.DevicePoints(scenes.CAUSTIC_LIGHT_OUTSIDE)
+    T = caustic.cull_sorted(ctx, m2, r2, l2)
+    i1, i2 = scenes.mixed_draw(len(w.q_tri), T.n, 2_000_000, 0.7, 4)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).cuda()  # noqa: E731
+    q1 = (dev(w.q_x0[i1]), dev(w.q_x2[i1]), dev(w.q_tri[i1]))
+    Q2 = T.take(torch.from_numpy(i2).cuda())
+    del T
+    prec = sp.SPOLY_FP32_POLISH64
+    a = ctx.solve_1bounce(m1, *p1, *q1, "R", 1.0, 1.0, prec)
+    b = ctx.solve_2bounce(m2, r2, l2, Q2.q0, Q2.q3, Q2.qt).copy()
+    b["query"] += len(i1)
+    ref = _key(np.concatenate([a, b]))
+    cap = len(ref) + 4096
+    out = torch.zeros(cap * sp.SOLUTION_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    queue = torch.zeros(1, dtype=torch.int64, device="cuda")
+    shape = sp.MixedShape(2, 1024, 2, 0)
+
+    def launch():
+        cnt.zero_()
+        queue.zero_()
+        ctx.solve_mixed(m1, *p1, *q1, "R", 1.0, 1.0, m2, r2, l2, Q2.q0, Q2.q3, Q2.qt, precision=prec, shape=shape,
+                        out=out, out_count=cnt, queue=queue, sync=False)
+
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        launch()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        launch()
+    for rep in range(2):
+        g.replay()
+        torch.cuda.synchronize()
+        n = int(cnt.item())
+        got = _key(out[: n * sp.SOLUTION_DTYPE.itemsize].cpu().numpy().view(sp.SOLUTION_DTYPE))
+        assert got.tobytes() == ref.tobytes(), rep
+    # one-vertex part against the FP64 oracle on a seeded sample of 20000 instances
+    smp = np.sort(np.random.default_rng(44).choice(len(i1), 20000, replace=False))
+    j = i1[smp]
+    orc, diag = oracle.solve_1bounce(w.mesh.P, w.mesh.N, w.mesh.tri, w.x0, w.x2, w.q_x0[j], w.q_x2[j], w.q_tri[j],
+                                     "R")
+    g1 = got[got["query"] < len(i1)]
+    pos = np.searchsorted(smp, g1["query"])
+    hit = (pos < len(smp)) & (smp[np.minimum(pos, len(smp) - 1)] == g1["query"])
+    g1 = g1[hit].copy()
+    g1["query"] = pos[hit]
+    st = parity.compare_onebounce(g1, orc, diag, len(smp), **parity.FP32)
+    print("mixed 2M: paths", len(got), "R sample vs oracle", st, flush=True)
+    assert st["compared"] > 20
+    ctx.close()
