@@ -25,6 +25,36 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_VALU = 78.6    # TFLOP/s: 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, fp32 (non-packed) and fp64
+PEAK_HBM = 8000.0   # GB/s
+
+# HBM bytes of one reflection solve (k_ob_front<float,R> + k_ob_back<R> + k_ob_full<float,R>) on the glints
+# workload, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch), scaled by what the same
+# counters read for a plain 256 MiB device copy (FETCH x2.0, WRITE x1.0).  Valid only for the kernel
+# sources they were taken on (sha256 prefix over the files in _KERNEL_SOURCES); otherwise traffic is null.
+TRAFFIC_R = {"sha": "318e8fd77b210c4c", "candidates": 99118927,
+             "fetch_kib": 619508.84 + 812240.97 + 254.22, "write_kib": 664032.23 + 488057.16 + 10.41,
+             "fetch_scale": 262144.0 / 131084.54, "write_scale": 262144.0 / 262144.0}
+_KERNEL_SOURCES = ("onebounce.hip", "spoly_dev.hpp", "laplace_gen.inc", "onebounce.hpp")
+
+
+def _kernel_sha() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in _KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2405_13409_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_bytes(candidates: int):
+    """HBM bytes per reflection-solve launch for `candidates` instances, or None
+    if the kernels changed since the counters were taken."""
+    t = TRAFFIC_R
+    if _kernel_sha() != t["sha"]:
+        return None
+    per = (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024.0 / t["candidates"]
+    return per * candidates
 PEAK_VALU_PACKED_FP32 = 157.3
 METRIC = "candidate solves/s & valid paths/s, pruned vs exhaustive at recall>=99.9%"
 
@@ -212,7 +242,7 @@ def main():
     dt = time.perf_counter() - t0
     ms_step = dt / args.steps * 1e3
 
-    # dominant kernel: the R solve (k_onebounce<float/double, R>)
+    # dominant kernel: the reflection solve (front + back + full-list kernels of one spoly_solve_1bounce call)
     rec = solve_ms["R"]
     avg_ms = float(np.mean([a.elapsed_time(b) for a, b, _ in rec]))
     n_r = rec[0][2]
@@ -245,12 +275,14 @@ def main():
         "stage_ms": {"solve_R": avg_ms, "solve_T": avg_ms_t},
         "roofline": {
             "bound": "alu",
-            "kernel": "k_onebounce<R>",
+            "kernel": "reflection solve: k_ob_front<float,R> + k_ob_back<R> + k_ob_full<float,R>",
             "achieved": achieved,
             "peak": PEAK_VALU,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_VALU,
-            "traffic": None,
+            "traffic": traffic_bytes(n_r),
+            "traffic_unit": "bytes per launch (HBM, FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "hbm_GBps": (traffic_bytes(n_r) / (avg_ms * 1e-3) / 1e9) if traffic_bytes(n_r) else None,
             "flops_per_instance": per_instance_flops("R"),
             "peak_note": "fp32/fp64 vector FMA without packed fp32 (packed-fp32 peak 157.3)",
         },
@@ -360,7 +392,7 @@ def caustic_leg(args, ctx):
     d0 = spoly.DevicePoints(rec)
     dl = spoly.DevicePoints(scenes.CAUSTIC_LIGHT_OUTSIDE)
     T = caustic.cull_sorted(ctx, dm, d0, dl)
-    r = caustic.prune_vs_exhaustive(ctx, dm, d0, dl, T, net, reps=3).as_dict()
+    r = caustic.prune_vs_exhaustive(ctx, dm, d0, dl, T, net, reps=2).as_dict()
     r["exhaustive_solves_per_s"] = r["n_tuples"] / r["ms_exhaustive"] * 1e3
     r["pruned_solves_per_s"] = r["n_tuples"] / r["ms_pruned"] * 1e3
     r["exhaustive_paths_per_s"] = r["paths_exhaustive"] / r["ms_exhaustive"] * 1e3

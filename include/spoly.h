@@ -162,6 +162,12 @@ spoly_status spoly_cull_1bounce(spoly_ctx *ctx, const spoly_mesh *mesh,
  * [3] reserved.
  * diag_q (optional, device int32 [2*n_queries]): per query the number of roots
  * of r(v) in [0,1] and the number of solutions.
+ * Runs as two kernels: the first finds the roots of r(v) and lists the
+ * candidates that have any in a workspace owned by ctx (28 bytes per query,
+ * grown on demand; growing synchronises the device); the second solves,
+ * polishes and validates the listed candidates.  Calls that share a
+ * context must therefore be issued on one stream.  E_DEVICE if the workspace
+ * cannot be allocated.
  */
 spoly_status spoly_solve_1bounce(spoly_ctx *ctx, const spoly_mesh *mesh,
                                  const spoly_points *x0s, const spoly_points *x2s,

@@ -21,6 +21,9 @@ struct spoly_ctx {
     unsigned long long* pair_count;
     spoly::PrunerWork pw;  // pruner training activations
     void* pw_block;
+    int cus;               // compute units of the device
+    void* ob_block;        // two-phase one-vertex workspace: items_q, items_n, items_v, count
+    int64_t ob_cap;
 };
 
 namespace {
@@ -79,6 +82,8 @@ spoly_status spoly_ctx_create(spoly_ctx** ctx, int device)
     spoly_ctx* c = static_cast<spoly_ctx*>(std::calloc(1, sizeof(spoly_ctx)));
     if (!c) return SPOLY_E_DEVICE;
     c->device = device;
+    if (hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || c->cus <= 0)
+        c->cus = 256;
     *ctx = c;
     return SPOLY_OK;
 }
@@ -90,7 +95,33 @@ void spoly_ctx_destroy(spoly_ctx* ctx)
     if (ctx->pairs) (void)hipFree(ctx->pairs);
     if (ctx->pair_count) (void)hipFree(ctx->pair_count);
     if (ctx->pw_block) (void)hipFree(ctx->pw_block);
+    if (ctx->ob_block) (void)hipFree(ctx->ob_block);
     std::free(ctx);
+}
+
+// Item list between the two phases of the one-vertex solve (grown on demand;
+// growing synchronises the device through hipFree/hipMalloc).
+static spoly_status ensure_ob_items(spoly_ctx* ctx, int64_t need, spoly::OneBounceArgs& A)
+{
+    if (ctx->ob_cap < need) {
+        if (ctx->ob_block) (void)hipFree(ctx->ob_block);
+        ctx->ob_block = nullptr;
+        ctx->ob_cap = 0;
+        const size_t bytes = size_t(need) * (12 + 8 * spoly::kObEmit) + 256;
+        if (hipMalloc(&ctx->ob_block, bytes) != hipSuccess) {
+            ctx->ob_block = nullptr;
+            return SPOLY_E_DEVICE;
+        }
+        ctx->ob_cap = need;
+    }
+    char* p = static_cast<char*>(ctx->ob_block);
+    A.items_count = reinterpret_cast<unsigned long long*>(p);
+    A.items_v = reinterpret_cast<double*>(p + 256);
+    A.items_q = reinterpret_cast<int32_t*>(p + 256 + size_t(ctx->ob_cap) * 8 * spoly::kObEmit);
+    A.items_n = A.items_q + ctx->ob_cap;
+    A.full_q = A.items_n + ctx->ob_cap;
+    A.items_cap = ctx->ob_cap;
+    return SPOLY_OK;
 }
 
 static spoly_status ensure_cones(spoly_ctx* ctx, const spoly_mesh* mesh, hipStream_t s)
@@ -161,7 +192,10 @@ spoly_status spoly_solve_1bounce(spoly_ctx* ctx, const spoly_mesh* mesh, const s
     A.polish_iters = params->polish_iters;
     A.out = out; A.cap = out_capacity; A.out_count = out_count;
     A.counters = counters; A.diag_q = diag_q;
-    return dev_err(spoly::launch_onebounce(A, int(ev), int(prec), static_cast<hipStream_t>(stream)));
+    const spoly_status st = ensure_ob_items(ctx, n_queries, A);
+    if (st != SPOLY_OK) return st;
+    return dev_err(spoly::launch_onebounce_2phase(A, int(ev), int(prec), ctx->cus * 4,
+                                                  static_cast<hipStream_t>(stream)));
 }
 
 }  // extern "C"
@@ -404,6 +438,8 @@ extern "C" spoly_status spoly_solve_mixed(spoly_ctx* ctx, const spoly_mesh* mesh
     A.polish_iters = params->polish_iters;
     A.out = out; A.cap = out_capacity; A.out_count = out_count;
     A.counters = nullptr; A.diag_q = nullptr;
+    A.items_q = nullptr; A.items_n = nullptr; A.items_v = nullptr; A.full_q = nullptr; A.items_cap = 0;
+    A.items_count = nullptr;
     spoly::TTArgs& T = M.t;
     T.px = mesh2->px; T.py = mesh2->py; T.pz = mesh2->pz;
     T.nx = mesh2->nx; T.ny = mesh2->ny; T.nz = mesh2->nz;

@@ -37,7 +37,7 @@ __global__ void __launch_bounds__(256) k_tri_cones(const double* px, const doubl
     cone[2 * t + 1] = make_float4(float(an.x), float(an.y), float(an.z), float(th + 1e-6));
 }
 
-constexpr int kCullPts = 64;  // (x0, x2) pairs per thread; one atomic per wave per 64 pairs
+constexpr int kCullPts = 256;  // (x0, x2) pairs per thread; one atomic per block of 256 x 256 tests
 
 // One side of the half-vector bound: the unit direction from the triangle's
 // bounding sphere (centre c, radius rad) towards point p, scaled by eta, and
@@ -88,12 +88,15 @@ __device__ __forceinline__ bool cone_meet(float4 c1, float cth, float sth, const
 
 // Grid: (pair block) x (triangle block of 256).  Each thread tests one
 // triangle against kCullPts consecutive (x0, x2) pairs, keeping the wave's
-// per-pair ballots in LDS; the wave then reserves its whole output range with
-// one atomic and writes the kept triples pair by pair (coalesced).  The x2
-// side of the bound is recomputed only when x2 changes (with one light: once).
+// per-pair ballots in LDS; the block then reserves its whole output range with
+// one atomic (a single counter shared by every block is the bottleneck when
+// each wave reserves on its own), and each wave writes its kept triples pair
+// by pair (coalesced).  The x2 side of the bound is recomputed only when x2
+// changes (with one light: once).
 __global__ void __launch_bounds__(256) k_cull_1bounce(CullArgs A)
 {
     __shared__ unsigned long long s_bal[4][kCullPts];
+    __shared__ unsigned long long s_slots[kMaxBlockWaves + 1];
     const int ntb = (A.n_tris + 255) / 256;
     const int t = int(blockIdx.x % ntb) * blockDim.x + threadIdx.x;
     const int64_t pblock = int64_t(blockIdx.x / ntb);
@@ -138,12 +141,8 @@ __global__ void __launch_bounds__(256) k_cull_1bounce(CullArgs A)
     }
     const int incl = wave_incl_scan(mine);
     const int total = __shfl(incl, kWave - 1, kWave);
+    const unsigned long long base = block_reserve((unsigned long long)total, A.out_count, s_slots);
     if (total == 0) return;
-    unsigned long long base = 0;
-    if (lane == kWave - 1) base = atomicAdd(A.out_count, (unsigned long long)total);
-    base = __shfl(base, kWave - 1, kWave);
-    __builtin_amdgcn_s_waitcnt(0);
-    __builtin_amdgcn_wave_barrier();
     unsigned long long off = base;
     const unsigned long long lt = (1ull << lane) - 1ull;
     int o0 = int(pair0 / A.n2), o2 = int(pair0 % A.n2);

@@ -292,9 +292,11 @@ __device__ __forceinline__ void push_sol(LaneSols& S, double u, double v, double
     if (S.n < kMaxLaneSol) S.n++;
 }
 
+// Coefficients, elimination and isolation: the roots of r(v) in [0,1] in
+// ascending order.  Returns their number (degen set for a degenerate instance).
 template <typename R, int EV, int F>
-__device__ __forceinline__ void solve_instance(const Geo& g, const OneBounceArgs& A, LaneSols& S, int& nvr,
-                                               int& ncand, int& degen)
+__device__ __forceinline__ int front_roots(const Geo& g, const OneBounceArgs& A, R (&rt)[Sys<R, EV, F>::DR + 1],
+                                           bool (&ok)[Sys<R, EV, F>::DR + 1], int& degen)
 {
     using Y = Sys<R, EV, F>;
     P2<R, Y::TA> a;
@@ -313,73 +315,95 @@ __device__ __forceinline__ void solve_instance(const Geo& g, const OneBounceArgs
     }
     if (!finite || !(rmax > R(0))) {
         degen = 1;
-        return;
+#pragma unroll
+        for (int k = 0; k <= Y::DR; ++k) ok[k] = false;
+        return 0;
     }
+    isolate01<R, Y::DR>(r, rt, ok, R(A.iso_eps));
+    int n = 0;
+#pragma unroll
+    for (int k = 0; k <= Y::DR; ++k) n += ok[k] ? 1 : 0;
+    return n;
+}
+
+// FP64 coefficients of a(u, v) as a polynomial in u (u-degree TA, constant leading term)
+template <int F>
+__device__ __forceinline__ P2<double, 1 + F> a_fp64(const Geo& g)
+{
+    VP<double, 1> x1 = vp_affine(g.p0, g.e1, g.e2);
+    auto n = NormalPoly<double, F>::make(g);
+    VP<double, 1> d0 = x1 - vp_const(g.x0);
+    return vdot(vcross(d0, vp_const(g.x2 - g.x0)), n);
+}
+
+// One root v of r: u from a(u)|v, FP64 polish, closed-triangle and path-space checks.
+template <int EV, int F>
+__device__ __forceinline__ void back_root(const Geo& g, const OneBounceArgs& A, const P2<double, 1 + F>& a64, double v,
+                                          LaneSols& S, int& ncand)
+{
+    constexpr int TA = 1 + F;
+    double c[TA + 1];
+#pragma unroll
+    for (int i = 0; i <= TA; ++i) {
+        double s = 0.0;
+#pragma unroll
+        for (int j = TA - i; j >= 0; --j) s = fma(s, v, a64.c[tri_idx(TA, i, j)]);
+        c[i] = s;
+    }
+    double us[2] = {0.0, 0.0};
+    int nu = 0;
+    if constexpr (TA == 2) {
+        double qa = c[2], qb = c[1], qc = c[0];
+        if (qa != 0.0) {
+            double disc = qb * qb - 4.0 * qa * qc;
+            if (disc > 0.0) {
+                double qq = -0.5 * (qb + copysign(sqrt(disc), qb));
+                double r1 = qq / qa, r2 = qc / qq;
+                us[0] = fmin(r1, r2);
+                us[1] = fmax(r1, r2);
+                nu = 2;
+            }
+        } else if (qb != 0.0) {
+            us[0] = -qc / qb;
+            nu = 1;
+        }
+    } else {
+        if (c[1] != 0.0) {
+            us[0] = -c[0] / c[1];
+            nu = 1;
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+        if (m >= nu) continue;
+        double u = us[m], vv = v;
+        if (!(u >= -A.u_margin && u <= 1.0 - v + A.u_margin)) continue;
+        ncand++;
+        if (!polish<EV>(g, A.eta0, A.eta1, A.polish_iters, u, vv)) continue;
+        if (!(u >= 0.0 && vv >= 0.0 && u + vv <= 1.0)) continue;
+        V3<double> x1 = g.p0 + g.e1 * u + g.e2 * vv;
+        V3<double> nn = g.n0 + g.dn1 * u + g.dn2 * vv;
+        double res;
+        if (!vertex_law(g.x0, x1, g.x2, nn, A.eta0, A.eta1, EV == SPOLY_T, res)) continue;
+        if (!(res <= A.tau)) continue;
+        double w = 1.0 - u - vv;
+        double edge = fmin(fmin(u, vv), w);
+        push_sol(S, u, vv, res, edge, A.dedup);
+    }
+}
+
+template <typename R, int EV, int F>
+__device__ __forceinline__ void solve_instance(const Geo& g, const OneBounceArgs& A, LaneSols& S, int& nvr,
+                                               int& ncand, int& degen)
+{
+    using Y = Sys<R, EV, F>;
     R rt[Y::DR + 1];
     bool ok[Y::DR + 1];
-    isolate01<R, Y::DR>(r, rt, ok, R(A.iso_eps));
-    // FP64 coefficients of a(u, v) as a polynomial in u (u-degree TA, constant leading term)
-    P2<double, Y::TA> a64;
-    {
-        VP<double, 1> x1 = vp_affine(g.p0, g.e1, g.e2);
-        auto n = NormalPoly<double, F>::make(g);
-        VP<double, 1> d0 = x1 - vp_const(g.x0);
-        a64 = vdot(vcross(d0, vp_const(g.x2 - g.x0)), n);
-    }
+    nvr += front_roots<R, EV, F>(g, A, rt, ok, degen);
+    const P2<double, 1 + F> a64 = a_fp64<F>(g);
 #pragma unroll
-    for (int k = 0; k <= Y::DR; ++k) {
-        if (!ok[k]) continue;
-        nvr++;
-        double v = double(rt[k]);
-        double c[Y::TA + 1];
-#pragma unroll
-        for (int i = 0; i <= Y::TA; ++i) {
-            double s = 0.0;
-#pragma unroll
-            for (int j = Y::TA - i; j >= 0; --j) s = fma(s, v, a64.c[tri_idx(Y::TA, i, j)]);
-            c[i] = s;
-        }
-        double us[2] = {0.0, 0.0};
-        int nu = 0;
-        if constexpr (Y::TA == 2) {
-            double qa = c[2], qb = c[1], qc = c[0];
-            if (qa != 0.0) {
-                double disc = qb * qb - 4.0 * qa * qc;
-                if (disc > 0.0) {
-                    double qq = -0.5 * (qb + copysign(sqrt(disc), qb));
-                    double r1 = qq / qa, r2 = qc / qq;
-                    us[0] = fmin(r1, r2);
-                    us[1] = fmax(r1, r2);
-                    nu = 2;
-                }
-            } else if (qb != 0.0) {
-                us[0] = -qc / qb;
-                nu = 1;
-            }
-        } else {
-            if (c[1] != 0.0) {
-                us[0] = -c[0] / c[1];
-                nu = 1;
-            }
-        }
-#pragma unroll
-        for (int m = 0; m < 2; ++m) {
-            if (m >= nu) continue;
-            double u = us[m], vv = v;
-            if (!(u >= -A.u_margin && u <= 1.0 - v + A.u_margin)) continue;
-            ncand++;
-            if (!polish<EV>(g, A.eta0, A.eta1, A.polish_iters, u, vv)) continue;
-            if (!(u >= 0.0 && vv >= 0.0 && u + vv <= 1.0)) continue;
-            V3<double> x1 = g.p0 + g.e1 * u + g.e2 * vv;
-            V3<double> nn = g.n0 + g.dn1 * u + g.dn2 * vv;
-            double res;
-            if (!vertex_law(g.x0, x1, g.x2, nn, A.eta0, A.eta1, EV == SPOLY_T, res)) continue;
-            if (!(res <= A.tau)) continue;
-            double w = 1.0 - u - vv;
-            double edge = fmin(fmin(u, vv), w);
-            push_sol(S, u, vv, res, edge, A.dedup);
-        }
-    }
+    for (int k = 0; k <= Y::DR; ++k)
+        if (ok[k]) back_root<EV, F>(g, A, a64, double(rt[k]), S, ncand);
 }
 
 __device__ __forceinline__ V3<double> ld3(const double* x, const double* y, const double* z, int i)
@@ -387,47 +411,46 @@ __device__ __forceinline__ V3<double> ld3(const double* x, const double* y, cons
     return {x[i], y[i], z[i]};
 }
 
-// One instance per lane; every lane of the wave must call it (the compaction
-// is wave-wide).  Output records carry query id q + qid_offset.
-template <typename R, int EV>
-__device__ __forceinline__ void onebounce_lane(const OneBounceArgs& A, int64_t q, bool active, int64_t qid_offset)
+// Geometry of query q (FP64), with the vertex relabelling of the product form.
+// Returns the triangle id.
+template <int EV>
+__device__ __forceinline__ int setup_geo(const OneBounceArgs& A, int64_t q, Geo& g)
 {
-    LaneSols S;
-    S.n = 0;
-    int nvr = 0, ncand = 0, degen = 0;
-    int tid = -1;
+    const int tid = A.q_tri[q];
+    const int i0 = A.tri[3 * tid], i1 = A.tri[3 * tid + 1], i2 = A.tri[3 * tid + 2];
+    V3<double> P0 = ld3(A.px, A.py, A.pz, i0), P1 = ld3(A.px, A.py, A.pz, i1), P2v = ld3(A.px, A.py, A.pz, i2);
+    V3<double> N0 = ld3(A.nx, A.ny, A.nz, i0), N1 = ld3(A.nx, A.ny, A.nz, i1), N2 = ld3(A.nx, A.ny, A.nz, i2);
+    const int j0 = A.q_x0[q], j2 = A.q_x2[q];
+    g.x0 = ld3(A.x0x, A.x0y, A.x0z, j0);
+    g.x2 = ld3(A.x2x, A.x2y, A.x2z, j2);
+    g.flat = N0.x == N1.x && N0.y == N1.y && N0.z == N1.z && N0.x == N2.x && N0.y == N2.y && N0.z == N2.z;
+    const V3<double> c = P0 + (P1 - P0) * (1.0 / 3.0) + (P2v - P0) * (1.0 / 3.0);
     bool swapped = false;
-    if (active) {
-        tid = A.q_tri[q];
-        int i0 = A.tri[3 * tid], i1 = A.tri[3 * tid + 1], i2 = A.tri[3 * tid + 2];
-        V3<double> P0 = ld3(A.px, A.py, A.pz, i0), P1 = ld3(A.px, A.py, A.pz, i1), P2v = ld3(A.px, A.py, A.pz, i2);
-        V3<double> N0 = ld3(A.nx, A.ny, A.nz, i0), N1 = ld3(A.nx, A.ny, A.nz, i1), N2 = ld3(A.nx, A.ny, A.nz, i2);
-        int j0 = A.q_x0[q], j2 = A.q_x2[q];
-        Geo g;
-        g.x0 = ld3(A.x0x, A.x0y, A.x0z, j0);
-        g.x2 = ld3(A.x2x, A.x2y, A.x2z, j2);
-        g.flat = N0.x == N1.x && N0.y == N1.y && N0.z == N1.z && N0.x == N2.x && N0.y == N2.y && N0.z == N2.z;
-        V3<double> c = P0 + (P1 - P0) * (1.0 / 3.0) + (P2v - P0) * (1.0 / 3.0);
-        if constexpr (EV == SPOLY_R) swapped = pick_edge2(c, g.x0, g.x2, P1 - P0, P2v - P0);
-        if (swapped) {
-            V3<double> t = P1; P1 = P2v; P2v = t;
-            t = N1; N1 = N2; N2 = t;
-        }
-        g.p0 = P0; g.e1 = P1 - P0; g.e2 = P2v - P0;
-        g.n0 = N0; g.dn1 = N1 - N0; g.dn2 = N2 - N0;
-        g.swapped = swapped;
-        g.axis = (EV == SPOLY_T) ? pick_axis(c, g.x0, g.x2) : 0;
-        bool finite = isfinite(dot(g.p0, g.e1) + dot(g.e2, g.n0) + dot(g.dn1, g.dn2) + dot(g.x0, g.x2));
-        if (!finite) degen = 1;
-        else if (g.flat) solve_instance<R, EV, 0>(g, A, S, nvr, ncand, degen);
-        else solve_instance<R, EV, 1>(g, A, S, nvr, ncand, degen);
+    if constexpr (EV == SPOLY_R) swapped = pick_edge2(c, g.x0, g.x2, P1 - P0, P2v - P0);
+    if (swapped) {
+        V3<double> t = P1; P1 = P2v; P2v = t;
+        t = N1; N1 = N2; N2 = t;
     }
-    // ---- compaction: one atomic per wave, records at base + exclusive prefix
+    g.p0 = P0; g.e1 = P1 - P0; g.e2 = P2v - P0;
+    g.n0 = N0; g.dn1 = N1 - N0; g.dn2 = N2 - N0;
+    g.swapped = swapped;
+    g.axis = (EV == SPOLY_T) ? pick_axis(c, g.x0, g.x2) : 0;
+    return tid;
+}
+
+// Solution records of one lane: compaction (block- or wave-wide), counters and
+// per-query diagnostics.  Every lane must call it.
+__device__ __forceinline__ void emit_lane(const OneBounceArgs& A, int64_t q, bool active, int64_t qid_offset, int tid,
+                                          bool swapped, const LaneSols& S, int nvr, int ncand, int degen,
+                                          unsigned long long* slots, bool write_nvr)
+{
     const int cnt = active ? S.n : 0;
     const int incl = wave_incl_scan(cnt);
     const int total = __shfl(incl, kWave - 1, kWave);
     unsigned long long base = 0;
-    if (total > 0) {
+    if (slots) {
+        base = block_reserve((unsigned long long)total, A.out_count, slots);
+    } else if (total > 0) {
         if (lane_id() == kWave - 1) base = atomicAdd(A.out_count, (unsigned long long)total);
         base = __shfl(base, kWave - 1, kWave);
     }
@@ -463,16 +486,205 @@ __device__ __forceinline__ void onebounce_lane(const OneBounceArgs& A, int64_t q
         }
     }
     if (A.diag_q && active) {
-        A.diag_q[2 * q] = nvr;
+        if (write_nvr) A.diag_q[2 * q] = nvr;
         A.diag_q[2 * q + 1] = S.n;
     }
+}
+
+// One instance per lane; every lane of the wave must call it (the compaction
+// is wave-wide).  Output records carry query id q + qid_offset.  With `slots`
+// (LDS, kMaxBlockWaves + 1 values) every thread of the block must call it and
+// the output range is reserved once per block; without, once per wave.
+template <typename R, int EV>
+__device__ __forceinline__ void onebounce_lane(const OneBounceArgs& A, int64_t q, bool active, int64_t qid_offset,
+                                               unsigned long long* slots = nullptr)
+{
+    LaneSols S;
+    S.n = 0;
+    int nvr = 0, ncand = 0, degen = 0;
+    int tid = -1;
+    bool swapped = false;
+    if (active) {
+        Geo g;
+        tid = setup_geo<EV>(A, q, g);
+        swapped = g.swapped;
+        bool finite = isfinite(dot(g.p0, g.e1) + dot(g.e2, g.n0) + dot(g.dn1, g.dn2) + dot(g.x0, g.x2));
+        if (!finite) degen = 1;
+        else if (g.flat) solve_instance<R, EV, 0>(g, A, S, nvr, ncand, degen);
+        else solve_instance<R, EV, 1>(g, A, S, nvr, ncand, degen);
+    }
+    emit_lane(A, q, active, qid_offset, tid, swapped, S, nvr, ncand, degen, slots, true);
 }
 
 template <typename R, int EV>
 __global__ void __launch_bounds__(256) k_onebounce(OneBounceArgs A)
 {
+    __shared__ unsigned long long s_slots[kMaxBlockWaves + 1];
     const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    onebounce_lane<R, EV>(A, q, q < A.nq, 0);
+    onebounce_lane<R, EV>(A, q, q < A.nq, 0, s_slots);
+}
+
+// ---------------------------------------------------------------- two-phase solve
+// Front: one candidate per lane; candidates with 1..kObEmit roots are appended
+// (block-wide reservation) to the item list; a candidate with more roots, or
+// one that finds the list full, is solved in place.
+template <typename R, int EV, int F>
+__device__ __forceinline__ int front_collect(const Geo& g, const OneBounceArgs& A, double (&vr)[kObEmit], int& degen)
+{
+    using Y = Sys<R, EV, F>;
+    R rt[Y::DR + 1];
+    bool ok[Y::DR + 1];
+    const int n = front_roots<R, EV, F>(g, A, rt, ok, degen);
+    int j = 0;
+#pragma unroll
+    for (int k = 0; k <= Y::DR; ++k) {
+        if (ok[k]) {
+#pragma unroll
+            for (int i = 0; i < kObEmit; ++i)
+                if (i == j) vr[i] = double(rt[k]);
+            ++j;
+        }
+    }
+    return n;
+}
+
+template <typename R, int EV>
+__global__ void __launch_bounds__(256) k_ob_front(OneBounceArgs A)
+{
+    __shared__ unsigned long long s_slots[kMaxBlockWaves + 1];
+    const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const bool active = q < A.nq;
+    int nvr = 0, degen = 0;
+    double vr[kObEmit];
+#pragma unroll
+    for (int i = 0; i < kObEmit; ++i) vr[i] = 0.0;
+    if (active) {
+        Geo g;
+        setup_geo<EV>(A, q, g);
+        const bool finite = isfinite(dot(g.p0, g.e1) + dot(g.e2, g.n0) + dot(g.dn1, g.dn2) + dot(g.x0, g.x2));
+        if (!finite) degen = 1;
+        else if (g.flat) nvr = front_collect<R, EV, 0>(g, A, vr, degen);
+        else nvr = front_collect<R, EV, 1>(g, A, vr, degen);
+    }
+    // one item per candidate with 1..kObEmit roots, one full-list entry per candidate with more
+    const bool want = active && nvr > 0 && nvr <= kObEmit;
+    const bool full = active && nvr > kObEmit;
+    const int wi = want ? 1 : 0, wf = full ? 1 : 0;
+    const int ii = wave_incl_scan(wi), fi = wave_incl_scan(wf);
+    const unsigned long long bi = block_reserve((unsigned long long)__shfl(ii, kWave - 1, kWave), A.items_count,
+                                                s_slots);
+    const unsigned long long bf = block_reserve((unsigned long long)__shfl(fi, kWave - 1, kWave),
+                                                A.items_count + 1, s_slots);
+    if (want) {
+        const unsigned long long idx = bi + (unsigned long long)(ii - wi);
+        A.items_q[idx] = int32_t(q);
+        A.items_n[idx] = nvr;
+#pragma unroll
+        for (int i = 0; i < kObEmit; ++i)
+            if (i < nvr) A.items_v[kObEmit * idx + i] = vr[i];
+    }
+    if (full) A.full_q[bf + (unsigned long long)(fi - wf)] = int32_t(q);
+    if (A.counters) {
+        const unsigned long long s0 = wave_sum_u64(active ? nvr : 0);
+        const unsigned long long s2 = wave_sum_u64(active ? degen : 0);
+        if (lane_id() == 0) {
+            if (s0) atomicAdd(A.counters + 0, s0);
+            if (s2) atomicAdd(A.counters + 2, s2);
+        }
+    }
+    if (A.diag_q && active) {
+        A.diag_q[2 * q] = nvr;
+        A.diag_q[2 * q + 1] = 0;
+    }
+}
+
+// Back: persistent blocks stride over the item list, one candidate per lane.
+template <int EV>
+__global__ void __launch_bounds__(256) k_ob_back(OneBounceArgs A)
+{
+    __shared__ unsigned long long s_slots[kMaxBlockWaves + 1];
+    const int64_t n_items = int64_t(*A.items_count);
+    for (int64_t b0 = int64_t(blockIdx.x) * blockDim.x; b0 < n_items; b0 += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t i = b0 + threadIdx.x;
+        const bool active = i < n_items;
+        LaneSols S;
+        S.n = 0;
+        int ncand = 0, tid = -1;
+        bool swapped = false;
+        int64_t q = 0;
+        if (active) {
+            q = A.items_q[i];
+            const int nr = A.items_n[i];
+            Geo g;
+            tid = setup_geo<EV>(A, q, g);
+            swapped = g.swapped;
+            if (g.flat) {
+                const P2<double, 1> a64 = a_fp64<0>(g);
+                for (int j = 0; j < nr; ++j) back_root<EV, 0>(g, A, a64, A.items_v[kObEmit * i + j], S, ncand);
+            } else {
+                const P2<double, 2> a64 = a_fp64<1>(g);
+                for (int j = 0; j < nr; ++j) back_root<EV, 1>(g, A, a64, A.items_v[kObEmit * i + j], S, ncand);
+            }
+        }
+        emit_lane(A, q, active, 0, tid, swapped, S, 0, ncand, 0, s_slots, false);
+    }
+}
+
+// The full list: candidates with more than kObEmit roots, solved from scratch.
+template <typename R, int EV>
+__global__ void __launch_bounds__(256) k_ob_full(OneBounceArgs A)
+{
+    __shared__ unsigned long long s_slots[kMaxBlockWaves + 1];
+    const int64_t n_full = int64_t(A.items_count[1]);
+    for (int64_t b0 = int64_t(blockIdx.x) * blockDim.x; b0 < n_full; b0 += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t i = b0 + threadIdx.x;
+        const bool active = i < n_full;
+        LaneSols S;
+        S.n = 0;
+        int ncand = 0, tid = -1, nv = 0, dg = 0;
+        bool swapped = false;
+        int64_t q = 0;
+        if (active) {
+            q = A.full_q[i];
+            Geo g;
+            tid = setup_geo<EV>(A, q, g);
+            swapped = g.swapped;
+            if (g.flat) solve_instance<R, EV, 0>(g, A, S, nv, ncand, dg);
+            else solve_instance<R, EV, 1>(g, A, S, nv, ncand, dg);
+        }
+        emit_lane(A, q, active, 0, tid, swapped, S, 0, ncand, 0, s_slots, false);
+    }
+}
+
+__global__ void k_zero_items(unsigned long long* p)
+{
+    p[0] = 0ull;
+    p[1] = 0ull;
+}
+
+hipError_t launch_onebounce_2phase(const OneBounceArgs& A, int ev, int prec, int back_blocks, hipStream_t stream)
+{
+    if (A.nq <= 0) return hipSuccess;
+    if (A.items_cap < A.nq) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_zero_items, dim3(1), dim3(1), 0, stream, A.items_count);
+    const dim3 block(256), grid(unsigned((A.nq + 255) / 256));
+    const dim3 bgrid(unsigned(back_blocks > 0 ? back_blocks : 1));
+    const dim3 fgrid(unsigned(back_blocks > 0 ? (back_blocks + 7) / 8 : 1));
+    // Refraction always runs in FP64 (see launch_onebounce).
+    if (ev == SPOLY_R && prec == SPOLY_FP64) {
+        hipLaunchKernelGGL((k_ob_front<double, SPOLY_R>), grid, block, 0, stream, A);
+        hipLaunchKernelGGL((k_ob_back<SPOLY_R>), bgrid, block, 0, stream, A);
+        hipLaunchKernelGGL((k_ob_full<double, SPOLY_R>), fgrid, block, 0, stream, A);
+    } else if (ev == SPOLY_R) {
+        hipLaunchKernelGGL((k_ob_front<float, SPOLY_R>), grid, block, 0, stream, A);
+        hipLaunchKernelGGL((k_ob_back<SPOLY_R>), bgrid, block, 0, stream, A);
+        hipLaunchKernelGGL((k_ob_full<float, SPOLY_R>), fgrid, block, 0, stream, A);
+    } else {
+        hipLaunchKernelGGL((k_ob_front<double, SPOLY_T>), grid, block, 0, stream, A);
+        hipLaunchKernelGGL((k_ob_back<SPOLY_T>), bgrid, block, 0, stream, A);
+        hipLaunchKernelGGL((k_ob_full<double, SPOLY_T>), fgrid, block, 0, stream, A);
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_onebounce(const OneBounceArgs& A, int ev, int prec, hipStream_t stream)

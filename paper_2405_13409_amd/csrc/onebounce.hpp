@@ -21,9 +21,26 @@ struct OneBounceArgs {
     unsigned long long* out_count;
     unsigned long long* counters;
     int32_t* diag_q;
+    // two-phase workspace (device), capacity items_cap >= nq each:
+    // candidates with 1..kObEmit roots of r(v), and candidates with more
+    int32_t* items_q;
+    int32_t* items_n;
+    double* items_v;              // [kObEmit * items_cap]
+    int32_t* full_q;
+    int64_t items_cap;
+    unsigned long long* items_count;   // [0] items, [1] full list
 };
 
+constexpr int kObEmit = 2;        // roots carried per candidate between the two phases
+
+// Fused single-kernel solve (used inside the persistent mixed kernel).
 hipError_t launch_onebounce(const OneBounceArgs& A, int ev, int prec, hipStream_t stream);
+// Two-phase solve: the front kernel finds the roots of r(v) and compacts the
+// candidates that have any into A.items_* (more than kObEmit roots: into
+// A.full_q); the back kernel (back_blocks persistent blocks) solves u,
+// polishes and validates the listed candidates with full waves, and a third
+// kernel solves the rare candidates of the full list from scratch.
+hipError_t launch_onebounce_2phase(const OneBounceArgs& A, int ev, int prec, int back_blocks, hipStream_t stream);
 
 struct CullArgs {
     const float4* tri_cone;   // per triangle: (centroid.xyz, radius), (axis.xyz, half angle)

@@ -209,4 +209,29 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x)
     return x;
 }
 
+// Output reservation shared by the waves of a block: every wave passes its
+// total; one atomic on *counter per block (instead of one per wave) returns
+// the block's base, and each wave receives base + the totals of the waves
+// before it.  All threads of the block must call it (it synchronises the
+// block); `slots` is LDS space for kMaxBlockWaves + 1 values.
+constexpr int kMaxBlockWaves = 16;
+__device__ __forceinline__ unsigned long long block_reserve(unsigned long long wave_total, unsigned long long* counter,
+                                                            unsigned long long* slots)
+{
+    const int w = threadIdx.x / kWave;
+    const int nw = (blockDim.x + kWave - 1) / kWave;
+    if (lane_id() == 0) slots[w] = wave_total;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long sum = 0;
+        for (int i = 0; i < nw; ++i) sum += slots[i];
+        slots[kMaxBlockWaves] = sum ? atomicAdd(counter, sum) : 0ull;
+    }
+    __syncthreads();
+    unsigned long long base = slots[kMaxBlockWaves];
+    for (int i = 0; i < w; ++i) base += slots[i];
+    __syncthreads();   // slots may be reused after this call
+    return base;
+}
+
 }  // namespace spoly

@@ -839,6 +839,7 @@ constexpr int kTTCullPts = 64;
 __global__ void __launch_bounds__(256) k_tt_cull(CullTTArgs A, int j3, int64_t n_pairs)
 {
     __shared__ unsigned long long s_bal[4][kTTCullPts];
+    __shared__ unsigned long long s_slots[kMaxBlockWaves + 1];
     const int64_t npb = (n_pairs + 255) / 256;
     const int64_t pk = int64_t(blockIdx.x % npb) * 256 + threadIdx.x;
     const int r0 = int(blockIdx.x / npb) * kTTCullPts;
@@ -874,12 +875,8 @@ __global__ void __launch_bounds__(256) k_tt_cull(CullTTArgs A, int j3, int64_t n
     }
     const int incl = wave_incl_scan(mine);
     const int total = __shfl(incl, kWave - 1, kWave);
+    const unsigned long long base = block_reserve((unsigned long long)total, A.out_count, s_slots);
     if (total == 0) return;
-    unsigned long long base = 0;
-    if (lane == kWave - 1) base = atomicAdd(A.out_count, (unsigned long long)total);
-    base = __shfl(base, kWave - 1, kWave);
-    __builtin_amdgcn_s_waitcnt(0);
-    __builtin_amdgcn_wave_barrier();
     unsigned long long off = base;
     const unsigned long long lt = (1ull << lane) - 1ull;
     for (int k = 0; k < nr; ++k) {
