@@ -656,27 +656,12 @@ __device__ __forceinline__ void tt_tuple(const TTArgs& A, int64_t q, double* lds
     const unsigned long long b_lo = __ballot(chg_lo), b_hi = __ballot(chg_hi);
     const int n_lo = __popcll(b_lo), n_hi = __popcll(b_hi);
     const int nv = n_lo + n_hi;
-    // ---- bisection (Sec. 5.2), then the path phase: lane k takes the k-th
-    // sign-change piece, runs the bisection steps on it (the v estimate is the
-    // final midpoint), solves u from a(u)|v, polishes and validates.
+    // ---- bisection (Sec. 5.2), then the path phase (u from a(u)|v, polish,
+    // validation) for the final midpoint of every sign-change piece.
     LaneTT S;
     S.n = 0;
     int ncand = 0;
-    for (int base = 0; base < nv; base += kWave) {
-        const int k = base + lane;
-        if (k >= nv) continue;
-        unsigned long long m = k < n_lo ? b_lo : b_hi;
-        const int r0 = k < n_lo ? k : k - n_lo;
-        for (int i = 0; i < r0; ++i) m &= m - 1ull;
-        const int piece = __ffsll((long long)m) - 1 + (k < n_lo ? 0 : kWave);
-        double l = double(piece) / P, r = double(piece + 1) / P;
-        const int sl = tt_det_sign(g, a.c, da, ma, l);
-        for (int it = 0; it < A.bisect_iters; ++it) {
-            const double mm = 0.5 * (l + r);
-            if (tt_det_sign(g, a.c, da, ma, mm) == sl) l = mm;
-            else r = mm;
-        }
-        const double v = 0.5 * (l + r);
+    auto path_phase = [&](const double v) {
         double c[kDA + 1];
         tt_acoef(a.c, da, ma, v, c);
         double ur[kDA + 1];
@@ -714,6 +699,94 @@ __device__ __forceinline__ void tt_tuple(const TTArgs& A, int64_t q, double* lds
                 }
             S.n++;
         }
+    };
+    // sign of the scan at grid point j (all lanes must call it)
+    auto scan_sign = [&](int j) -> int {
+        const int lo = __shfl(s_lo, j & (kWave - 1), kWave);
+        const int hi = __shfl(s_hi, j & (kWave - 1), kWave);
+        return j < kWave ? lo : hi;
+    };
+    auto kth_piece = [&](int k) -> int {
+        unsigned long long m = k < n_lo ? b_lo : b_hi;
+        const int r0 = k < n_lo ? k : k - n_lo;
+        for (int i = 0; i < r0; ++i) m &= m - 1ull;
+        return __ffsll((long long)m) - 1 + (k < n_lo ? 0 : kWave);
+    };
+    // Bits per round of the grouped bisection: groups of 2^b lanes evaluate the
+    // 2^b - 1 midpoints that the next b bisection steps can visit, so b steps
+    // cost one evaluation round; 64 / 2^b pieces share a round.  Chosen per
+    // tuple for the fewest rounds; b = 1 is the plain one-lane-per-piece loop.
+    const int iters = A.bisect_iters;
+    int bits = 1;
+    if (nv > 0 && nv <= 32 && iters > 0) {
+        int best = iters * ((nv + kWave - 1) / kWave);
+        for (int bb = 2; bb <= 5; ++bb) {
+            const int rounds = (iters + bb - 1) / bb, per = kWave >> bb;
+            const int cost = rounds * ((nv + per - 1) / per);
+            if (cost < best) { best = cost; bits = bb; }
+        }
+    }
+    if (bits == 1) {
+        for (int base = 0; base < nv; base += kWave) {
+            const int k = base + lane;
+            const int piece = k < nv ? kth_piece(k) : 0;
+            const int sl = scan_sign(piece);
+            if (k >= nv) continue;
+            double l = double(piece) / P, r = double(piece + 1) / P;
+            for (int it = 0; it < iters; ++it) {
+                const double mm = 0.5 * (l + r);
+                if (tt_det_sign(g, a.c, da, ma, mm) == sl) l = mm;
+                else r = mm;
+            }
+            path_phase(0.5 * (l + r));
+        }
+    } else {
+        // Every round reproduces b sequential steps exactly: the candidate
+        // midpoints are formed by the same halvings, and the step decisions
+        // read the signs evaluated at them.
+        const int gsz = 1 << bits, per = kWave >> bits;
+        const int grp = lane >> bits, j = lane & (gsz - 1);
+        double my_v = 0.0;
+        for (int batch = 0; batch < nv; batch += per) {
+            const int k = batch + grp;
+            const bool act = k < nv;
+            const int piece = act ? kth_piece(k) : 0;
+            const int sl = scan_sign(piece);
+            double l = double(piece) / P, r = double(piece + 1) / P;
+            for (int left = iters; left > 0;) {
+                const int bb = left < bits ? left : bits;
+                const int top = 1 << (bb - 1);
+                bool same = false;
+                if (act && j >= 1 && j < (1 << bb)) {
+                    double lo = l, hi = r, pt = 0.0;
+                    int c = top, half = top >> 1;
+                    for (int d = 0; d < bb; ++d) {   // node j of the in-order tree sits at depth < bb
+                        const double mm = 0.5 * (lo + hi);
+                        if (j == c) { pt = mm; break; }
+                        if (j > c) { lo = mm; c += half; }
+                        else { hi = mm; c -= half; }
+                        half >>= 1;
+                    }
+                    same = tt_det_sign(g, a.c, da, ma, pt) == sl;
+                }
+                const unsigned long long bal = __ballot(same);
+                const unsigned int gb = (unsigned int)((bal >> (grp << bits)) & ((1ull << gsz) - 1ull));
+                int c = top, half = top >> 1;
+                for (int st = 0; st < bb; ++st) {
+                    const double mm = 0.5 * (l + r);
+                    if ((gb >> c) & 1u) { l = mm; c += half; }
+                    else { r = mm; c -= half; }
+                    half >>= 1;
+                }
+                left -= bb;
+            }
+            const double v = 0.5 * (l + r);
+            // hand the piece's v to lane k (lanes batch .. batch + per - 1)
+            const int t = lane - batch;
+            const double got = __shfl(v, (t >= 0 && t < per ? t : 0) << bits, kWave);
+            if (t >= 0 && t < per && lane < nv) my_v = got;
+        }
+        if (lane < nv) path_phase(my_v);
     }
     // ---- de-duplicate across lanes (two v roots polishing onto one path), then compact
     // lanes compare against all earlier lanes' solutions through shuffles
