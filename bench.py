@@ -147,7 +147,7 @@ def main():
                     help="comma list: glints (the headline line), mixed (2M-instance persistent launch), "
                          "caustic (learned pruner against the exhaustive two-vertex solve)")
     ap.add_argument("--mixed-total", type=int, default=2_000_000)
-    ap.add_argument("--caustic-stride", type=int, default=16, help="every k-th receiver of the 64x64 grid")
+    ap.add_argument("--caustic-stride", type=int, default=1, help="every k-th receiver of the 64x64 grid")
     ap.add_argument("--pruner", default=None, help="trained pruner .npz (default: the packaged weights)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy 5 times (the reference kernel for scaling "
@@ -392,7 +392,7 @@ def caustic_leg(args, ctx):
     d0 = spoly.DevicePoints(rec)
     dl = spoly.DevicePoints(scenes.CAUSTIC_LIGHT_OUTSIDE)
     T = caustic.cull_sorted(ctx, dm, d0, dl)
-    r = caustic.prune_vs_exhaustive(ctx, dm, d0, dl, T, net, reps=2).as_dict()
+    r = caustic.prune_vs_exhaustive(ctx, dm, d0, dl, T, net, reps=3, exhaustive_reps=1).as_dict()
     r["exhaustive_solves_per_s"] = r["n_tuples"] / r["ms_exhaustive"] * 1e3
     r["pruned_solves_per_s"] = r["n_tuples"] / r["ms_pruned"] * 1e3
     r["exhaustive_paths_per_s"] = r["paths_exhaustive"] / r["ms_exhaustive"] * 1e3

@@ -72,9 +72,11 @@ class PruneReport:
         return d
 
 
-def _timed(fn, reps: int):
-    """Median device time (ms) of fn() over reps runs, after one warm-up."""
-    fn()
+def _timed(fn, reps: int, warmup: bool = True):
+    """Median device time (ms) of fn() over reps runs, after one warm-up run
+    unless warmup is False."""
+    if warmup:
+        fn()
     ms = []
     for _ in range(reps):
         a = torch.cuda.Event(enable_timing=True)
@@ -87,14 +89,20 @@ def _timed(fn, reps: int):
     return float(np.median(ms))
 
 
-def prune_vs_exhaustive(ctx, dm, d0, d3, T: pr.Tuples, net: pr.Pruner, reps: int = 3, eta=ETA) -> PruneReport:
+def prune_vs_exhaustive(ctx, dm, d0, d3, T: pr.Tuples, net: pr.Pruner, reps: int = 3, eta=ETA,
+                        exhaustive_reps: int | None = None) -> PruneReport:
     """Exhaustive solve of every tuple against score + solve of the kept ones.
-    Recall is measured against the exhaustive solve's own labels."""
+    Recall is measured against the exhaustive solve's own labels.  With
+    exhaustive_reps set, the (long) exhaustive solve runs exactly that many
+    times, without a warm-up run."""
     n = T.n
     cap = max(4096, n // 64)
     out = torch.empty(cap * spoly.SOLUTION_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
     cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
-    ms_ex = _timed(lambda: solve_count(ctx, dm, d0, d3, T, out, cnt, eta), reps)
+    if exhaustive_reps is None:
+        ms_ex = _timed(lambda: solve_count(ctx, dm, d0, d3, T, out, cnt, eta), reps)
+    else:
+        ms_ex = _timed(lambda: solve_count(ctx, dm, d0, d3, T, out, cnt, eta), exhaustive_reps, warmup=False)
     n_ex = int(cnt.item())
     if n_ex > cap:
         raise spoly.SpolyError(f"solution capacity {cap} < {n_ex}")

@@ -86,19 +86,43 @@ __device__ __forceinline__ bool cone_meet(float4 c1, float cth, float sth, const
     return cdot >= clim * (1.0f - 4e-6f);
 }
 
+// Position of the r-th set bit (r counted from 0) of a 64-bit mask.
+__device__ __forceinline__ int select_bit(unsigned long long m, int r)
+{
+    int pos = 0;
+    int c = __popc(unsigned(m));
+    if (r >= c) { r -= c; m >>= 32; pos += 32; }
+    unsigned x = unsigned(m);
+    c = __popc(x & 0xffffu);
+    if (r >= c) { r -= c; x >>= 16; pos += 16; }
+    c = __popc(x & 0xffu);
+    if (r >= c) { r -= c; x >>= 8; pos += 8; }
+    c = __popc(x & 0xfu);
+    if (r >= c) { r -= c; x >>= 4; pos += 4; }
+    c = __popc(x & 0x3u);
+    if (r >= c) { r -= c; x >>= 2; pos += 2; }
+    if (r >= int(x & 1u)) pos += 1;
+    return pos;
+}
+
 // Grid: (pair block) x (triangle block of 256).  Each thread tests one
 // triangle against kCullPts consecutive (x0, x2) pairs, keeping the wave's
-// per-pair ballots in LDS; the block then reserves its whole output range with
+// per-pair ballots in LDS.  The block reserves its whole output range with
 // one atomic (a single counter shared by every block is the bottleneck when
-// each wave reserves on its own), and each wave writes its kept triples pair
-// by pair (coalesced).  The x2 side of the bound is recomputed only when x2
-// changes (with one light: once).
+// each wave reserves on its own).  Each wave then writes its kept triples in
+// (pair, lane) order with full-width stores: output slot s of the wave is
+// mapped back to its pair by a binary search over the per-pair prefix counts
+// and to its lane by selecting the right bit of that pair's ballot.  The x2
+// side of the bound is recomputed only when x2 changes (with one light: once).
 __global__ void __launch_bounds__(256) k_cull_1bounce(CullArgs A)
 {
     __shared__ unsigned long long s_bal[4][kCullPts];
+    __shared__ int s_cum[4][kCullPts];
+    __shared__ int s_j0[kCullPts], s_j2[kCullPts];
     __shared__ unsigned long long s_slots[kMaxBlockWaves + 1];
     const int ntb = (A.n_tris + 255) / 256;
-    const int t = int(blockIdx.x % ntb) * blockDim.x + threadIdx.x;
+    const int t0 = int(blockIdx.x % ntb) * blockDim.x;
+    const int t = t0 + threadIdx.x;
     const int64_t pblock = int64_t(blockIdx.x / ntb);
     const bool tri_ok = t < A.n_tris;
     const int w = threadIdx.x / kWave;
@@ -132,7 +156,13 @@ __global__ void __launch_bounds__(256) k_cull_1bounce(CullArgs A)
             keep = all || !a_ok || !b_ok || cone_meet(c1, cth, sth, sa, sb);
         }
         const unsigned long long bal = __ballot(keep);
-        if (lane == 0) s_bal[w][k] = bal;
+        if (lane == 0) {
+            s_bal[w][k] = bal;
+            if (w == 0) {
+                s_j0[k] = j0;
+                s_j2[k] = j2;
+            }
+        }
         mine += keep ? 1 : 0;
         if (++j2 == A.n2) {
             j2 = 0;
@@ -141,25 +171,39 @@ __global__ void __launch_bounds__(256) k_cull_1bounce(CullArgs A)
     }
     const int incl = wave_incl_scan(mine);
     const int total = __shfl(incl, kWave - 1, kWave);
-    const unsigned long long base = block_reserve((unsigned long long)total, A.out_count, s_slots);
-    if (total == 0) return;
-    unsigned long long off = base;
-    const unsigned long long lt = (1ull << lane) - 1ull;
-    int o0 = int(pair0 / A.n2), o2 = int(pair0 % A.n2);
-    for (int k = 0; k < npairs; ++k) {
-        const unsigned long long bal = s_bal[w][k];
-        if ((bal >> lane) & 1ull) {
-            const unsigned long long idx = off + (unsigned long long)__popcll(bal & lt);
-            if (idx < (unsigned long long)A.cap) {
-                A.out_x0[idx] = o0;
-                A.out_x2[idx] = o2;
-                A.out_tri[idx] = t;
-            }
+    __syncthreads();   // ballots and pair indices visible to every lane
+    // exclusive per-pair prefix counts of this wave (4 pairs per lane)
+    {
+        constexpr int kPer = kCullPts / kWave;
+        int cnt[kPer], sum = 0;
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int k = lane * kPer + i;
+            cnt[i] = k < npairs ? __popcll(s_bal[w][k]) : 0;
+            sum += cnt[i];
         }
-        off += (unsigned long long)__popcll(bal);
-        if (++o2 == A.n2) {
-            o2 = 0;
-            ++o0;
+        int run = wave_incl_scan(sum) - sum;
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            s_cum[w][lane * kPer + i] = run;
+            run += cnt[i];
+        }
+    }
+    const unsigned long long base = block_reserve((unsigned long long)total, A.out_count, s_slots);
+    for (int sidx = lane; sidx < total; sidx += kWave) {
+        // last pair k with s_cum[k] <= sidx
+        int lo = 0, hi = npairs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_cum[w][mid] <= sidx) lo = mid;
+            else hi = mid - 1;
+        }
+        const int src = select_bit(s_bal[w][lo], sidx - s_cum[w][lo]);
+        const unsigned long long idx = base + (unsigned long long)sidx;
+        if (idx < (unsigned long long)A.cap) {
+            A.out_x0[idx] = s_j0[lo];
+            A.out_x2[idx] = s_j2[lo];
+            A.out_tri[idx] = t0 + w * kWave + src;
         }
     }
 }

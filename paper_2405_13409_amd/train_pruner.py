@@ -1,6 +1,6 @@
 """Train the learned two-vertex tuple pruner on the caustic scene.
 
-    python -m paper_2405_13409_amd.train_pruner --out paper_2405_13409_amd/weights/caustic_pruner.npz
+    python -m paper_2405_13409_amd.train_pruner --eval --out paper_2405_13409_amd/weights/caustic_pruner.npz
 
 Training data: receivers x0 ~ U([-2,2]^2) at z = -1 (seeded), the light
 outside the sphere.  Every cone-culled tuple of every receiver is solved
@@ -94,15 +94,15 @@ def evaluate(ctx, dm, dl, net: pr.Pruner, receivers: np.ndarray, chunk: int = 25
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--receivers", type=int, default=4096)
+    ap.add_argument("--receivers", type=int, default=8192)
     ap.add_argument("--examples", type=int, default=4_000_000)
-    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--steps", type=int, default=6000)
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--pos-weight", type=float, default=20.0)
     ap.add_argument("--pos-frac", type=float, default=0.25)
     ap.add_argument("--recall", type=float, default=0.999)
-    ap.add_argument("--slack", type=float, default=0.5)
+    ap.add_argument("--slack", type=float, default=0.1)
     ap.add_argument("--seed", type=int, default=5)
     ap.add_argument("--eval", action="store_true", help="also measure on the 64x64 receiver grid")
     ap.add_argument("--eval-stride", type=int, default=1, help="use every k-th grid receiver in --eval")
