@@ -162,10 +162,10 @@ spoly_status spoly_cull_1bounce(spoly_ctx *ctx, const spoly_mesh *mesh,
  * [3] reserved.
  * diag_q (optional, device int32 [2*n_queries]): per query the number of roots
  * of r(v) in [0,1] and the number of solutions.
- * Runs as two kernels: the first finds the roots of r(v) and lists the
+ * Runs in two phases: the front finds the roots of r(v) and lists the
  * candidates that have any in a workspace owned by ctx (28 bytes per query,
- * grown on demand; growing synchronises the device); the second solves,
- * polishes and validates the listed candidates.  Calls that share a
+ * for refraction 112 more; grown on demand, and growing synchronises the
+ * device); the back solves, polishes and validates the listed candidates.  Calls that share a
  * context must therefore be issued on one stream.  E_DEVICE if the workspace
  * cannot be allocated.
  */

@@ -22,8 +22,10 @@ struct spoly_ctx {
     spoly::PrunerWork pw;  // pruner training activations
     void* pw_block;
     int cus;               // compute units of the device
-    void* ob_block;        // two-phase one-vertex workspace: items_q, items_n, items_v, count
+    void* ob_block;        // two-phase one-vertex workspace: counters, items, full list
     int64_t ob_cap;
+    void* ob_rblock;       // r(v) of the candidates listed for isolation, list and status
+    int64_t ob_rbytes;
 };
 
 namespace {
@@ -96,24 +98,33 @@ void spoly_ctx_destroy(spoly_ctx* ctx)
     if (ctx->pair_count) (void)hipFree(ctx->pair_count);
     if (ctx->pw_block) (void)hipFree(ctx->pw_block);
     if (ctx->ob_block) (void)hipFree(ctx->ob_block);
+    if (ctx->ob_rblock) (void)hipFree(ctx->ob_rblock);
     std::free(ctx);
 }
 
-// Item list between the two phases of the one-vertex solve (grown on demand;
-// growing synchronises the device through hipFree/hipMalloc).
-static spoly_status ensure_ob_items(spoly_ctx* ctx, int64_t need, spoly::OneBounceArgs& A)
+// Item list between the two phases of the one-vertex solve, and for
+// refraction the per-candidate r(v) between its coefficient and isolation
+// kernels (grown on demand; growing synchronises the device through
+// hipFree/hipMalloc).
+static spoly_status grow(void** block, int64_t* cap, int64_t need, size_t per, size_t head)
 {
-    if (ctx->ob_cap < need) {
-        if (ctx->ob_block) (void)hipFree(ctx->ob_block);
-        ctx->ob_block = nullptr;
-        ctx->ob_cap = 0;
-        const size_t bytes = size_t(need) * (12 + 8 * spoly::kObEmit) + 256;
-        if (hipMalloc(&ctx->ob_block, bytes) != hipSuccess) {
-            ctx->ob_block = nullptr;
-            return SPOLY_E_DEVICE;
-        }
-        ctx->ob_cap = need;
+    if (*cap >= need) return SPOLY_OK;
+    if (*block) (void)hipFree(*block);
+    *block = nullptr;
+    *cap = 0;
+    if (hipMalloc(block, size_t(need) * per + head) != hipSuccess) {
+        *block = nullptr;
+        return SPOLY_E_DEVICE;
     }
+    *cap = need;
+    return SPOLY_OK;
+}
+
+static spoly_status ensure_ob_items(spoly_ctx* ctx, int64_t need, size_t coef_bytes, spoly::OneBounceArgs& A)
+{
+    // [256 B counters | items_v: kObEmit doubles | items_q, items_n, full_q: int32] per candidate
+    spoly_status st = grow(&ctx->ob_block, &ctx->ob_cap, need, 8 * spoly::kObEmit + 12, 256);
+    if (st != SPOLY_OK) return st;
     char* p = static_cast<char*>(ctx->ob_block);
     A.items_count = reinterpret_cast<unsigned long long*>(p);
     A.items_v = reinterpret_cast<double*>(p + 256);
@@ -121,6 +132,25 @@ static spoly_status ensure_ob_items(spoly_ctx* ctx, int64_t need, spoly::OneBoun
     A.items_n = A.items_q + ctx->ob_cap;
     A.full_q = A.items_n + ctx->ob_cap;
     A.items_cap = ctx->ob_cap;
+    // [r(v) of listed candidates: coef_bytes | iso_q, iso_st: int32] per candidate, same capacity
+    A.rlist = nullptr;
+    A.iso_q = nullptr;
+    A.iso_st = nullptr;
+    if (coef_bytes == 0) return SPOLY_OK;
+    const int64_t per = int64_t(coef_bytes) + 8;
+    if (ctx->ob_rbytes < per * ctx->ob_cap) {
+        if (ctx->ob_rblock) (void)hipFree(ctx->ob_rblock);
+        ctx->ob_rblock = nullptr;
+        ctx->ob_rbytes = 0;
+        if (hipMalloc(&ctx->ob_rblock, size_t(per) * size_t(ctx->ob_cap)) != hipSuccess) {
+            ctx->ob_rblock = nullptr;
+            return SPOLY_E_DEVICE;
+        }
+        ctx->ob_rbytes = per * ctx->ob_cap;
+    }
+    A.rlist = ctx->ob_rblock;
+    A.iso_q = reinterpret_cast<int32_t*>(static_cast<char*>(ctx->ob_rblock) + size_t(coef_bytes) * ctx->ob_cap);
+    A.iso_st = A.iso_q + ctx->ob_cap;
     return SPOLY_OK;
 }
 
@@ -192,7 +222,10 @@ spoly_status spoly_solve_1bounce(spoly_ctx* ctx, const spoly_mesh* mesh, const s
     A.polish_iters = params->polish_iters;
     A.out = out; A.cap = out_capacity; A.out_count = out_count;
     A.counters = counters; A.diag_q = diag_q;
-    const spoly_status st = ensure_ob_items(ctx, n_queries, A);
+    A.refine_v = (ev == SPOLY_R && prec == SPOLY_FP32_POLISH64) ? 1 : 0;
+    // the refraction front lists r(v) (13 doubles) of candidates between its two kernels
+    const size_t coef_bytes = ev == SPOLY_T ? 13 * 8 : 0;
+    const spoly_status st = ensure_ob_items(ctx, n_queries, coef_bytes, A);
     if (st != SPOLY_OK) return st;
     return dev_err(spoly::launch_onebounce_2phase(A, int(ev), int(prec), ctx->cus * 4,
                                                   static_cast<hipStream_t>(stream)));
@@ -436,9 +469,11 @@ extern "C" spoly_status spoly_solve_mixed(spoly_ctx* ctx, const spoly_mesh* mesh
     A.eta0 = eta0; A.eta1 = eta1;
     A.iso_eps = params->iso_eps; A.tau = params->tau; A.u_margin = params->u_margin; A.dedup = params->dedup;
     A.polish_iters = params->polish_iters;
+    A.refine_v = (ev1 == SPOLY_R && prec == SPOLY_FP32_POLISH64) ? 1 : 0;
     A.out = out; A.cap = out_capacity; A.out_count = out_count;
     A.counters = nullptr; A.diag_q = nullptr;
     A.items_q = nullptr; A.items_n = nullptr; A.items_v = nullptr; A.full_q = nullptr; A.items_cap = 0;
+    A.rlist = nullptr; A.iso_q = nullptr; A.iso_st = nullptr;
     A.items_count = nullptr;
     spoly::TTArgs& T = M.t;
     T.px = mesh2->px; T.py = mesh2->py; T.pz = mesh2->pz;

@@ -9,6 +9,7 @@
 namespace spoly {
 
 constexpr int kMaxLaneSol = 4;
+constexpr double kNearDoubleU = 1e-3;   // u-root pairs closer than this are tried from their midpoint
 
 struct Geo {            // FP64 geometry of one instance (after the edge relabelling)
     V3<double> p0, e1, e2, n0, dn1, dn2, x0, x2;
@@ -292,11 +293,10 @@ __device__ __forceinline__ void push_sol(LaneSols& S, double u, double v, double
     if (S.n < kMaxLaneSol) S.n++;
 }
 
-// Coefficients, elimination and isolation: the roots of r(v) in [0,1] in
-// ascending order.  Returns their number (degen set for a degenerate instance).
+// Coefficients and elimination: r(v), normalised.  Returns false for a
+// degenerate instance (r not finite or identically zero).
 template <typename R, int EV, int F>
-__device__ __forceinline__ int front_roots(const Geo& g, const OneBounceArgs& A, R (&rt)[Sys<R, EV, F>::DR + 1],
-                                           bool (&ok)[Sys<R, EV, F>::DR + 1], int& degen)
+__device__ __forceinline__ bool front_poly(const Geo& g, const OneBounceArgs& A, R (&r)[Sys<R, EV, F>::DR + 1])
 {
     using Y = Sys<R, EV, F>;
     P2<R, Y::TA> a;
@@ -304,7 +304,6 @@ __device__ __forceinline__ int front_roots(const Geo& g, const OneBounceArgs& A,
     build_ab<R, EV, F>(g, A.eta0, A.eta1, a, b);
     normalise(a);
     normalise(b);
-    R r[Y::DR + 1];
     eliminate<R, EV, F>(a.c, b.c, r);
     R rmax = R(0);
     bool finite = true;
@@ -313,12 +312,38 @@ __device__ __forceinline__ int front_roots(const Geo& g, const OneBounceArgs& A,
         rmax = fmax(rmax, fabs(r[k]));
         finite = finite && isfinite(r[k]);
     }
-    if (!finite || !(rmax > R(0))) {
+    return finite && rmax > R(0);
+}
+
+// r(v) not finite or identically zero (the test front_poly applies)
+template <typename R, int D>
+__device__ __forceinline__ bool front_poly_degenerate(const R (&r)[D + 1])
+{
+    R rmax = R(0);
+    bool finite = true;
+#pragma unroll
+    for (int k = 0; k <= D; ++k) {
+        rmax = fmax(rmax, fabs(r[k]));
+        finite = finite && isfinite(r[k]);
+    }
+    return !(finite && rmax > R(0));
+}
+
+// Coefficients, elimination and isolation: the roots of r(v) in [0,1] in
+// ascending order.  Returns their number (degen set for a degenerate instance).
+template <typename R, int EV, int F>
+__device__ __forceinline__ int front_roots(const Geo& g, const OneBounceArgs& A, R (&rt)[Sys<R, EV, F>::DR + 1],
+                                           bool (&ok)[Sys<R, EV, F>::DR + 1], int& degen)
+{
+    using Y = Sys<R, EV, F>;
+    R r[Y::DR + 1];
+    if (!front_poly<R, EV, F>(g, A, r)) {
         degen = 1;
 #pragma unroll
         for (int k = 0; k <= Y::DR; ++k) ok[k] = false;
         return 0;
     }
+
     isolate01<R, Y::DR>(r, rt, ok, R(A.iso_eps));
     int n = 0;
 #pragma unroll
@@ -336,12 +361,89 @@ __device__ __forceinline__ P2<double, 1 + F> a_fp64(const Geo& g)
     return vdot(vcross(d0, vp_const(g.x2 - g.x0)), n);
 }
 
+// Determinant of the Bezout matrix of a(., v0) and b(., v0) for reflection,
+// evaluated in FP64 from the geometry at a fixed v0: the same construction as
+// the generated elimination (B_ij = sum_k a_{i-k} b_{j+1+k} - b_{i-k} a_{j+1+k},
+// b truncated at the Bezout size), i.e. r(v0) up to a positive factor.
+template <int F>
+__device__ __forceinline__ double bezout_det_r(const Geo& g, double v0)
+{
+    constexpr int N = 1 + 2 * F;
+    const V3<double> P = g.p0 + g.e2 * v0;
+    const V3<double> E = g.e1, w = g.x2 - g.x0;
+    const V3<double> N0 = F ? g.n0 + g.dn2 * v0 : g.n0;
+    const V3<double> N1 = F ? g.dn1 : V3<double>{0.0, 0.0, 0.0};
+    const V3<double> D0 = P - g.x0, D1 = g.x2 - P;
+    const V3<double> A0 = cross(D0, w), A1 = cross(E, w);
+    double a[4] = {dot(A0, N0), dot(A0, N1) + dot(A1, N0), dot(A1, N1), 0.0};
+    const V3<double> T0 = cross(N0, E), T1 = cross(N1, E);
+    const double dn[3] = {dot(D0, N0), dot(D0, N1) + dot(E, N0), dot(E, N1)};
+    const double d1t[3] = {dot(D1, T0), dot(D1, T1) - dot(E, T0), -dot(E, T1)};
+    const double d0t[3] = {dot(D0, T0), dot(D0, T1) + dot(E, T0), dot(E, T1)};
+    const double d1n[3] = {dot(D1, N0), dot(D1, N1) - dot(E, N0), -dot(E, N1)};
+    double b[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) b[i + j] += dn[i] * d1t[j] + d0t[i] * d1n[j];
+    auto av = [&](int p) { return p <= 2 ? a[p] : 0.0; };
+    auto bv = [&](int p) { return p <= N ? b[p] : 0.0; };
+    double B[N][N];
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            double e = 0.0;
+#pragma unroll
+            for (int k = 0; k <= (i < N - 1 - j ? i : N - 1 - j); ++k) {
+                const int pp = i - k, qq = j + 1 + k;
+                if (pp != qq) e += av(pp) * bv(qq) - bv(pp) * av(qq);
+            }
+            B[i][j] = e;
+        }
+    double det;
+    if constexpr (N == 1) {
+        det = B[0][0];
+    } else {
+        det = B[0][0] * (B[1][1] * B[2][2] - B[1][2] * B[2][1]) - B[0][1] * (B[1][0] * B[2][2] - B[1][2] * B[2][0]) +
+              B[0][2] * (B[1][0] * B[2][1] - B[1][1] * B[2][0]);
+    }
+    return det;
+}
+
+// FP64 refinement of a root v of r found in FP32: secant iterations on the
+// FP64 Bezout determinant started at v and v + 1e-6 (up to six; two suffice
+// from an FP32-accurate root).  FP32 coefficients can move a simple root by
+// ~1e-3 when the elimination cancels, and u from a(u)|v is only as good as v.
+// The FP32 value is kept if the iteration leaves [v - 0.05, v + 0.05].
+template <int F>
+__device__ __forceinline__ double refine_v64(const Geo& g, double v)
+{
+    double xa = v, xb = v + 1e-6;
+    double fa = bezout_det_r<F>(g, xa), fb = bezout_det_r<F>(g, xb);
+    for (int it = 0; it < 6; ++it) {
+        const double den = fb - fa;
+        if (!(den != 0.0) || !isfinite(den)) break;
+        const double xn = xb - fb * (xb - xa) / den;
+        if (!(fabs(xn - v) <= 0.05)) return v;
+        xa = xb;
+        fa = fb;
+        xb = xn;
+        fb = bezout_det_r<F>(g, xb);
+        if (fb == 0.0 || fabs(xb - xa) <= 4e-16 * fmax(1.0, fabs(xb))) break;
+    }
+    return isfinite(xb) && fabs(xb - v) <= 0.05 ? xb : v;
+}
+
 // One root v of r: u from a(u)|v, FP64 polish, closed-triangle and path-space checks.
 template <int EV, int F>
 __device__ __forceinline__ void back_root(const Geo& g, const OneBounceArgs& A, const P2<double, 1 + F>& a64, double v,
                                           LaneSols& S, int& ncand)
 {
     constexpr int TA = 1 + F;
+    if constexpr (EV == SPOLY_R) {
+        if (A.refine_v) v = refine_v64<F>(g, v);
+    }
     double c[TA + 1];
 #pragma unroll
     for (int i = 0; i <= TA; ++i) {
@@ -362,6 +464,15 @@ __device__ __forceinline__ void back_root(const Geo& g, const OneBounceArgs& A, 
                 us[0] = fmin(r1, r2);
                 us[1] = fmax(r1, r2);
                 nu = 2;
+            } else if (-disc <= kNearDoubleU * kNearDoubleU * qa * qa) {
+                // The two u roots are within kNearDoubleU of each other or a
+                // complex pair that close to the real axis: v is known only to
+                // the isolation tolerance, so a solution with a near-double u
+                // root can show a slightly negative discriminant.  Its vertex
+                // is the start point; the FP64 polish (whose Jacobian does not
+                // vanish there at a simple solution) and validation decide.
+                us[0] = -qb / (2.0 * qa);
+                nu = 1;
             }
         } else if (qb != 0.0) {
             us[0] = -qc / qb;
@@ -528,16 +639,12 @@ __global__ void __launch_bounds__(256) k_onebounce(OneBounceArgs A)
 // Front: one candidate per lane; candidates with 1..kObEmit roots are appended
 // (block-wide reservation) to the item list; a candidate with more roots, or
 // one that finds the list full, is solved in place.
-template <typename R, int EV, int F>
-__device__ __forceinline__ int front_collect(const Geo& g, const OneBounceArgs& A, double (&vr)[kObEmit], int& degen)
+template <typename R, int D>
+__device__ __forceinline__ void gather_roots(const R (&rt)[D + 1], const bool (&ok)[D + 1], double (&vr)[kObEmit])
 {
-    using Y = Sys<R, EV, F>;
-    R rt[Y::DR + 1];
-    bool ok[Y::DR + 1];
-    const int n = front_roots<R, EV, F>(g, A, rt, ok, degen);
     int j = 0;
 #pragma unroll
-    for (int k = 0; k <= Y::DR; ++k) {
+    for (int k = 0; k <= D; ++k) {
         if (ok[k]) {
 #pragma unroll
             for (int i = 0; i < kObEmit; ++i)
@@ -545,30 +652,30 @@ __device__ __forceinline__ int front_collect(const Geo& g, const OneBounceArgs& 
             ++j;
         }
     }
+}
+
+template <typename R, int EV, int F>
+__device__ __forceinline__ int front_collect(const Geo& g, const OneBounceArgs& A, double (&vr)[kObEmit], int& degen,
+                                             bool& uncertain)
+{
+    using Y = Sys<R, EV, F>;
+    R rt[Y::DR + 1];
+    bool ok[Y::DR + 1];
+    const int n = front_roots<R, EV, F>(g, A, rt, ok, degen);
+    uncertain = false;
+    gather_roots<R, Y::DR>(rt, ok, vr);
     return n;
 }
 
-template <typename R, int EV>
-__global__ void __launch_bounds__(256) k_ob_front(OneBounceArgs A)
+// Item emission of the front phase (every thread of the block must call it):
+// one item per candidate with 1..kObEmit roots, one full-list entry per
+// candidate with more, counters and per-query diagnostics.
+__device__ __forceinline__ void emit_items(const OneBounceArgs& A, int64_t q, bool active, int nvr, int degen,
+                                           const double (&vr)[kObEmit], unsigned long long* s_slots,
+                                           bool force_full = false)
 {
-    __shared__ unsigned long long s_slots[kMaxBlockWaves + 1];
-    const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    const bool active = q < A.nq;
-    int nvr = 0, degen = 0;
-    double vr[kObEmit];
-#pragma unroll
-    for (int i = 0; i < kObEmit; ++i) vr[i] = 0.0;
-    if (active) {
-        Geo g;
-        setup_geo<EV>(A, q, g);
-        const bool finite = isfinite(dot(g.p0, g.e1) + dot(g.e2, g.n0) + dot(g.dn1, g.dn2) + dot(g.x0, g.x2));
-        if (!finite) degen = 1;
-        else if (g.flat) nvr = front_collect<R, EV, 0>(g, A, vr, degen);
-        else nvr = front_collect<R, EV, 1>(g, A, vr, degen);
-    }
-    // one item per candidate with 1..kObEmit roots, one full-list entry per candidate with more
-    const bool want = active && nvr > 0 && nvr <= kObEmit;
-    const bool full = active && nvr > kObEmit;
+    const bool full = active && (nvr > kObEmit || force_full);
+    const bool want = active && !full && nvr > 0;
     const int wi = want ? 1 : 0, wf = full ? 1 : 0;
     const int ii = wave_incl_scan(wi), fi = wave_incl_scan(wf);
     const unsigned long long bi = block_reserve((unsigned long long)__shfl(ii, kWave - 1, kWave), A.items_count,
@@ -595,6 +702,170 @@ __global__ void __launch_bounds__(256) k_ob_front(OneBounceArgs A)
     if (A.diag_q && active) {
         A.diag_q[2 * q] = nvr;
         A.diag_q[2 * q + 1] = 0;
+    }
+}
+
+// Fused front (reflection): coefficients, elimination and isolation in one
+// kernel of 86 VGPRs (five waves per SIMD), one candidate per lane.
+template <typename R, int EV>
+__global__ void __launch_bounds__(256) k_ob_front(OneBounceArgs A)
+{
+    __shared__ unsigned long long s_slots[kMaxBlockWaves + 1];
+    const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const bool active = q < A.nq;
+    int nvr = 0, degen = 0;
+    bool uncertain = false;
+    double vr[kObEmit];
+#pragma unroll
+    for (int i = 0; i < kObEmit; ++i) vr[i] = 0.0;
+    if (active) {
+        Geo g;
+        setup_geo<EV>(A, q, g);
+        const bool finite = isfinite(dot(g.p0, g.e1) + dot(g.e2, g.n0) + dot(g.dn1, g.dn2) + dot(g.x0, g.x2));
+        if (!finite) degen = 1;
+        else if (g.flat) nvr = front_collect<R, EV, 0>(g, A, vr, degen, uncertain);
+        else nvr = front_collect<R, EV, 1>(g, A, vr, degen, uncertain);
+    }
+    emit_items(A, q, active, nvr, degen, vr, s_slots, uncertain);
+}
+
+// Front phase in two kernels (refraction).  k_ob_coef builds r(v) for every candidate and
+// lists, in list order, the candidates whose r may have a root in [0,1]
+// (their r and a status: 0 interpolated normals, 1 flat).  k_ob_iso isolates
+// the listed ones with full waves and emits items.  The split keeps the
+// isolation off the lanes of the ~70% of candidates without a root, and it
+// separates the FP64 elimination (which needs every vector register) from the
+// isolation (three waves per SIMD).  For reflection in FP32 the fused front
+// is faster: its elimination is light and the list traffic would cost more
+// than the isolation it saves.
+//
+// Exclusion test: with Bernstein coefficients b_k of r on [0,1],
+// r(v) = sum_k b_k B_k(v) with B_k >= 0 and sum_k B_k = 1, so r(v) >= min_k b_k
+// (and <= max_k b_k) on [0,1].  If every b_k exceeds `margin` in the same
+// sign, where margin bounds the rounding of the b_k and of the Horner
+// evaluations of the isolation (about (3 D + 4) units in the last place of
+// sum |r_j|), the isolation cannot see a sign change and the candidate has no
+// root of r in [0,1].
+template <typename R, int D>
+__device__ __forceinline__ bool no_root01(const R (&r)[D + 1])
+{
+    R l1 = R(0);
+#pragma unroll
+    for (int j = 0; j <= D; ++j) l1 += fabs(r[j]);
+    const R margin = (sizeof(R) == 4 ? R(1e-5) : R(1e-13)) * l1;
+    bool pos = true, neg = true;
+#pragma unroll
+    for (int k = 0; k <= D; ++k) {
+        R bk = R(0);
+#pragma unroll
+        for (int j = 0; j <= k; ++j) bk = fma(R(binom(k, j) / binom(D, j)), r[j], bk);
+        pos = pos && bk > margin;
+        neg = neg && bk < -margin;
+    }
+    return pos || neg;
+}
+
+// r(v) of listed candidate i, coefficient k: rlist[k * cap + i]
+template <typename R, int EV, int F>
+__device__ __forceinline__ bool coef_list(const Geo& g, const OneBounceArgs& A, R (&r)[Sys<R, EV, F>::DR + 1])
+{
+    return front_poly<R, EV, F>(g, A, r) && !no_root01<R, Sys<R, EV, F>::DR>(r);
+}
+
+template <typename R, int EV>
+__global__ void __launch_bounds__(256) k_ob_coef(OneBounceArgs A)
+{
+    __shared__ unsigned long long s_slots[kMaxBlockWaves + 1];
+    constexpr int D1 = Sys<R, EV, 1>::DR, D0 = Sys<R, EV, 0>::DR;
+    const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const bool active = q < A.nq;
+    int degen = 0, flat = 0;
+    bool listed = false;
+    R r[D1 + 1];
+#pragma unroll
+    for (int k = 0; k <= D1; ++k) r[k] = R(0);
+    if (active) {
+        Geo g;
+        setup_geo<EV>(A, q, g);
+        const bool finite = isfinite(dot(g.p0, g.e1) + dot(g.e2, g.n0) + dot(g.dn1, g.dn2) + dot(g.x0, g.x2));
+        if (!finite) {
+            degen = 1;
+        } else if (g.flat) {
+            flat = 1;
+            R r0[D0 + 1];
+            listed = coef_list<R, EV, 0>(g, A, r0);
+            degen = front_poly_degenerate<R, D0>(r0) ? 1 : 0;
+#pragma unroll
+            for (int k = 0; k <= D0; ++k) r[k] = r0[k];
+        } else {
+            listed = coef_list<R, EV, 1>(g, A, r);
+            degen = front_poly_degenerate<R, D1>(r) ? 1 : 0;
+        }
+    }
+    const int wl = listed ? 1 : 0;
+    const int il = wave_incl_scan(wl);
+    const unsigned long long bl = block_reserve((unsigned long long)__shfl(il, kWave - 1, kWave),
+                                                A.items_count + 2, s_slots);
+    if (listed) {
+        const unsigned long long i = bl + (unsigned long long)(il - wl);
+        R* rl = reinterpret_cast<R*>(A.rlist);
+        A.iso_q[i] = int32_t(q);
+        A.iso_st[i] = flat;
+#pragma unroll
+        for (int k = 0; k <= D1; ++k)
+            if (!flat || k <= D0) rl[k * A.items_cap + i] = r[k];
+    }
+    if (A.counters) {
+        const unsigned long long s2 = wave_sum_u64(active ? degen : 0);
+        if (lane_id() == 0 && s2) atomicAdd(A.counters + 2, s2);
+    }
+    if (A.diag_q && active && !listed) {
+        A.diag_q[2 * q] = 0;
+        A.diag_q[2 * q + 1] = 0;
+    }
+}
+
+// Three waves per SIMD is the register target at which the FP64 isolation
+// compiles without scratch (about 160 VGPRs); left to itself the compiler
+// uses all 512 registers of one wave.
+template <typename R, int EV>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_ob_iso(OneBounceArgs A)
+{
+    __shared__ unsigned long long s_slots[kMaxBlockWaves + 1];
+    constexpr int D1 = Sys<R, EV, 1>::DR, D0 = Sys<R, EV, 0>::DR;
+    const R* rl = reinterpret_cast<const R*>(A.rlist);
+    const int64_t n_list = int64_t(A.items_count[2]);
+    for (int64_t b0 = int64_t(blockIdx.x) * blockDim.x; b0 < n_list; b0 += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t i = b0 + threadIdx.x;
+        const bool active = i < n_list;
+        int nvr = 0;
+        int64_t q = 0;
+        double vr[kObEmit];
+#pragma unroll
+        for (int k = 0; k < kObEmit; ++k) vr[k] = 0.0;
+        if (active) {
+            q = A.iso_q[i];
+            if (A.iso_st[i] == 1) {
+                R r[D0 + 1], rt[D0 + 1];
+                bool ok[D0 + 1];
+#pragma unroll
+                for (int k = 0; k <= D0; ++k) r[k] = rl[k * A.items_cap + i];
+                isolate01<R, D0>(r, rt, ok, R(A.iso_eps));
+#pragma unroll
+                for (int k = 0; k <= D0; ++k) nvr += ok[k] ? 1 : 0;
+                gather_roots<R, D0>(rt, ok, vr);
+            } else {
+                R r[D1 + 1], rt[D1 + 1];
+                bool ok[D1 + 1];
+#pragma unroll
+                for (int k = 0; k <= D1; ++k) r[k] = rl[k * A.items_cap + i];
+                isolate01<R, D1>(r, rt, ok, R(A.iso_eps));
+#pragma unroll
+                for (int k = 0; k <= D1; ++k) nvr += ok[k] ? 1 : 0;
+                gather_roots<R, D1>(rt, ok, vr);
+            }
+        }
+        emit_items(A, q, active, nvr, 0, vr, s_slots);
     }
 }
 
@@ -630,8 +901,9 @@ __global__ void __launch_bounds__(256) k_ob_back(OneBounceArgs A)
     }
 }
 
-// The full list: candidates with more than kObEmit roots, solved from scratch.
-template <typename R, int EV>
+// The full list: candidates with more than kObEmit roots, and FP32 candidates
+// whose root count the FP64 check doubts, solved from scratch in FP64.
+template <int EV>
 __global__ void __launch_bounds__(256) k_ob_full(OneBounceArgs A)
 {
     __shared__ unsigned long long s_slots[kMaxBlockWaves + 1];
@@ -649,8 +921,8 @@ __global__ void __launch_bounds__(256) k_ob_full(OneBounceArgs A)
             Geo g;
             tid = setup_geo<EV>(A, q, g);
             swapped = g.swapped;
-            if (g.flat) solve_instance<R, EV, 0>(g, A, S, nv, ncand, dg);
-            else solve_instance<R, EV, 1>(g, A, S, nv, ncand, dg);
+            if (g.flat) solve_instance<double, EV, 0>(g, A, S, nv, ncand, dg);
+            else solve_instance<double, EV, 1>(g, A, S, nv, ncand, dg);
         }
         emit_lane(A, q, active, 0, tid, swapped, S, 0, ncand, 0, s_slots, false);
     }
@@ -658,14 +930,15 @@ __global__ void __launch_bounds__(256) k_ob_full(OneBounceArgs A)
 
 __global__ void k_zero_items(unsigned long long* p)
 {
-    p[0] = 0ull;
-    p[1] = 0ull;
+    p[0] = 0ull;   // items
+    p[1] = 0ull;   // full list
+    p[2] = 0ull;   // refraction: candidates listed for isolation
 }
 
 hipError_t launch_onebounce_2phase(const OneBounceArgs& A, int ev, int prec, int back_blocks, hipStream_t stream)
 {
     if (A.nq <= 0) return hipSuccess;
-    if (A.items_cap < A.nq) return hipErrorInvalidValue;
+    if (A.items_cap < A.nq || (ev == SPOLY_T && !A.rlist)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_zero_items, dim3(1), dim3(1), 0, stream, A.items_count);
     const dim3 block(256), grid(unsigned((A.nq + 255) / 256));
     const dim3 bgrid(unsigned(back_blocks > 0 ? back_blocks : 1));
@@ -674,15 +947,16 @@ hipError_t launch_onebounce_2phase(const OneBounceArgs& A, int ev, int prec, int
     if (ev == SPOLY_R && prec == SPOLY_FP64) {
         hipLaunchKernelGGL((k_ob_front<double, SPOLY_R>), grid, block, 0, stream, A);
         hipLaunchKernelGGL((k_ob_back<SPOLY_R>), bgrid, block, 0, stream, A);
-        hipLaunchKernelGGL((k_ob_full<double, SPOLY_R>), fgrid, block, 0, stream, A);
+        hipLaunchKernelGGL((k_ob_full<SPOLY_R>), fgrid, block, 0, stream, A);
     } else if (ev == SPOLY_R) {
         hipLaunchKernelGGL((k_ob_front<float, SPOLY_R>), grid, block, 0, stream, A);
         hipLaunchKernelGGL((k_ob_back<SPOLY_R>), bgrid, block, 0, stream, A);
-        hipLaunchKernelGGL((k_ob_full<float, SPOLY_R>), fgrid, block, 0, stream, A);
+        hipLaunchKernelGGL((k_ob_full<SPOLY_R>), fgrid, block, 0, stream, A);
     } else {
-        hipLaunchKernelGGL((k_ob_front<double, SPOLY_T>), grid, block, 0, stream, A);
+        hipLaunchKernelGGL((k_ob_coef<double, SPOLY_T>), grid, block, 0, stream, A);
+        hipLaunchKernelGGL((k_ob_iso<double, SPOLY_T>), bgrid, block, 0, stream, A);
         hipLaunchKernelGGL((k_ob_back<SPOLY_T>), bgrid, block, 0, stream, A);
-        hipLaunchKernelGGL((k_ob_full<double, SPOLY_T>), fgrid, block, 0, stream, A);
+        hipLaunchKernelGGL((k_ob_full<SPOLY_T>), fgrid, block, 0, stream, A);
     }
     return hipGetLastError();
 }

@@ -16,6 +16,7 @@ struct OneBounceArgs {
     double eta0, eta1;
     double iso_eps, tau, u_margin, dedup;
     int32_t polish_iters;
+    int32_t refine_v;             // refine each root v of r in FP64 before the u solve (FP32 reflection)
     spoly_solution* out;
     int64_t cap;
     unsigned long long* out_count;
@@ -27,19 +28,25 @@ struct OneBounceArgs {
     int32_t* items_n;
     double* items_v;              // [kObEmit * items_cap]
     int32_t* full_q;
+    void* rlist;                  // r(v) of the listed candidates, [k][list index], float or double
+    int32_t* iso_q;               // listed candidates (query ids)
+    int32_t* iso_st;              // listed candidates: 0 interpolated normals, 1 flat
     int64_t items_cap;
-    unsigned long long* items_count;   // [0] items, [1] full list
+    unsigned long long* items_count;   // [0] items, [1] full list, [2] isolation list
 };
 
 constexpr int kObEmit = 2;        // roots carried per candidate between the two phases
+constexpr int kObCoefMax = 13;    // largest number of coefficients of r(v) (refraction, interpolated normals)
 
 // Fused single-kernel solve (used inside the persistent mixed kernel).
 hipError_t launch_onebounce(const OneBounceArgs& A, int ev, int prec, hipStream_t stream);
-// Two-phase solve: the front kernel finds the roots of r(v) and compacts the
-// candidates that have any into A.items_* (more than kObEmit roots: into
-// A.full_q); the back kernel (back_blocks persistent blocks) solves u,
-// polishes and validates the listed candidates with full waves, and a third
-// kernel solves the rare candidates of the full list from scratch.
+// Two-phase solve.  Front: a coefficient kernel builds r(v) and lists the
+// candidates that may have a root in [0,1] (Bernstein test), an isolation
+// kernel finds the roots of the listed ones and compacts the candidates with
+// 1..kObEmit roots into A.items_* (more roots: A.full_q).  Back: a persistent
+// kernel (back_blocks blocks) solves u, polishes and validates the items with
+// full waves, and a last kernel solves the rare candidates of the full list
+// from scratch.
 hipError_t launch_onebounce_2phase(const OneBounceArgs& A, int ev, int prec, int back_blocks, hipStream_t stream);
 
 struct CullArgs {

@@ -188,6 +188,14 @@ __device__ __forceinline__ R horner(const R (&c)[D + 1], R x)
     return s;
 }
 
+// binomial coefficient C(n, k) as a double (exact for the small n used here)
+__host__ __device__ constexpr double binom(int n, int k)
+{
+    double r = 1.0;
+    for (int i = 1; i <= k; ++i) r = r * double(n - k + i) / double(i);
+    return r;
+}
+
 // ------------------------------------------------------------------ wave64 primitives
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 

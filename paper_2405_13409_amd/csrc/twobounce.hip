@@ -339,12 +339,6 @@ __device__ int tt_udeg(LP a)
 // whose piece ends are the roots of the level below; each piece with a strict
 // sign change (sgn(0) := +1) is solved by safeguarded Newton (bisection
 // fallback keeps the bracket) to full precision.
-__host__ __device__ constexpr double binom(int n, int k)
-{
-    double r = 1.0;
-    for (int i = 1; i <= k; ++i) r = r * double(n - k + i) / double(i);
-    return r;
-}
 
 // f and f' of the level polynomial q_k = c[k+m] C(k+m, m), k = 0..d (the m-th
 // derivative of sum c_k x^k divided by m!), read straight from c.
