@@ -27,13 +27,13 @@ sys.path.insert(0, ROOT)
 PEAK_VALU = 78.6    # TFLOP/s: 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, fp32 (non-packed) and fp64
 PEAK_HBM = 8000.0   # GB/s
 
-# HBM bytes of one reflection solve (k_ob_front<float,R> + k_ob_back<R> + k_ob_full<float,R>) on the glints
+# HBM bytes of one reflection solve (k_ob_front<float,R> + k_ob_back<R> + k_ob_full<R>) on the glints
 # workload, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch), scaled by what the same
 # counters read for a plain 256 MiB device copy (FETCH x2.0, WRITE x1.0).  Valid only for the kernel
 # sources they were taken on (sha256 prefix over the files in _KERNEL_SOURCES); otherwise traffic is null.
-TRAFFIC_R = {"sha": "318e8fd77b210c4c", "candidates": 99118927,
-             "fetch_kib": 619508.84 + 812240.97 + 254.22, "write_kib": 664032.23 + 488057.16 + 10.41,
-             "fetch_scale": 262144.0 / 131084.54, "write_scale": 262144.0 / 262144.0}
+TRAFFIC_R = {"sha": "32bc90d5c4e0562b", "candidates": 99118927,
+             "fetch_kib": 619429.38 + 813770.63 + 280.16, "write_kib": 664015.81 + 488060.03 + 10.41,
+             "fetch_scale": 262144.0 / 131084.48, "write_scale": 262144.0 / 262144.0}
 _KERNEL_SOURCES = ("onebounce.hip", "spoly_dev.hpp", "laplace_gen.inc", "onebounce.hpp")
 
 
@@ -275,7 +275,7 @@ def main():
         "stage_ms": {"solve_R": avg_ms, "solve_T": avg_ms_t},
         "roofline": {
             "bound": "alu",
-            "kernel": "reflection solve: k_ob_front<float,R> + k_ob_back<R> + k_ob_full<float,R>",
+            "kernel": "reflection solve: k_ob_front<float,R> + k_ob_back<R> + k_ob_full<R>",
             "achieved": achieved,
             "peak": PEAK_VALU,
             "unit": "TFLOP/s",

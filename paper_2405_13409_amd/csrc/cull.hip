@@ -121,90 +121,95 @@ __global__ void __launch_bounds__(256) k_cull_1bounce(CullArgs A)
     __shared__ int s_j0[kCullPts], s_j2[kCullPts];
     __shared__ unsigned long long s_slots[kMaxBlockWaves + 1];
     const int ntb = (A.n_tris + 255) / 256;
-    const int t0 = int(blockIdx.x % ntb) * blockDim.x;
-    const int t = t0 + threadIdx.x;
-    const int64_t pblock = int64_t(blockIdx.x / ntb);
-    const bool tri_ok = t < A.n_tris;
-    const int w = threadIdx.x / kWave;
-    const int lane = lane_id();
-    float4 c0 = make_float4(0, 0, 0, 0), c1 = make_float4(0, 0, 0, 4.0f);
-    if (tri_ok) {
-        c0 = A.tri_cone[2 * t];
-        c1 = A.tri_cone[2 * t + 1];
-    }
-    // a normal cone of 90 degrees or more (with the margin) meets every h
-    const float thm = c1.w + A.margin;
-    const bool all = !(thm < 1.5707f);
-    const float cth = cosf(fminf(thm, 1.5707f)), sth = sinf(fminf(thm, 1.5707f));
-    const int64_t n_pairs = int64_t(A.n0) * A.n2;
-    const int64_t pair0 = pblock * kCullPts;
-    const int npairs = int(min<int64_t>(kCullPts, n_pairs - pair0));
-    int j0 = int(pair0 / A.n2), j2 = int(pair0 % A.n2);
-    int j2_side = -1;
-    ConeSide sb{0.0f, 0.0f, 0.0f, 0.0f};
-    bool b_ok = false;
-    int mine = 0;
-    for (int k = 0; k < npairs; ++k) {
-        bool keep = false;
+    const int64_t nblk = ((int64_t(A.n0) * A.n2 + kCullPts - 1) / kCullPts) * ntb;
+    // grid-stride over (pair block, triangle block): a launch may hold at most 2^32 work-items
+    for (int64_t vb = blockIdx.x; vb < nblk; vb += gridDim.x) {
+        const int t0 = int(vb % ntb) * blockDim.x;
+        const int t = t0 + threadIdx.x;
+        const int64_t pblock = vb / ntb;
+        const bool tri_ok = t < A.n_tris;
+        const int w = threadIdx.x / kWave;
+        const int lane = lane_id();
+        float4 c0 = make_float4(0, 0, 0, 0), c1 = make_float4(0, 0, 0, 4.0f);
         if (tri_ok) {
-            if (j2 != j2_side) {
-                b_ok = cone_side(c0, float(A.x2x[j2]), float(A.x2y[j2]), float(A.x2z[j2]), A.eta1, sb);
-                j2_side = j2;
+            c0 = A.tri_cone[2 * t];
+            c1 = A.tri_cone[2 * t + 1];
+        }
+        // a normal cone of 90 degrees or more (with the margin) meets every h
+        const float thm = c1.w + A.margin;
+        const bool all = !(thm < 1.5707f);
+        const float cth = cosf(fminf(thm, 1.5707f)), sth = sinf(fminf(thm, 1.5707f));
+        const int64_t n_pairs = int64_t(A.n0) * A.n2;
+        const int64_t pair0 = pblock * kCullPts;
+        const int npairs = int(min<int64_t>(kCullPts, n_pairs - pair0));
+        int j0 = int(pair0 / A.n2), j2 = int(pair0 % A.n2);
+        int j2_side = -1;
+        ConeSide sb{0.0f, 0.0f, 0.0f, 0.0f};
+        bool b_ok = false;
+        int mine = 0;
+        for (int k = 0; k < npairs; ++k) {
+            bool keep = false;
+            if (tri_ok) {
+                if (j2 != j2_side) {
+                    b_ok = cone_side(c0, float(A.x2x[j2]), float(A.x2y[j2]), float(A.x2z[j2]), A.eta1, sb);
+                    j2_side = j2;
+                }
+                ConeSide sa;
+                const bool a_ok = cone_side(c0, float(A.x0x[j0]), float(A.x0y[j0]), float(A.x0z[j0]), A.eta0, sa);
+                keep = all || !a_ok || !b_ok || cone_meet(c1, cth, sth, sa, sb);
             }
-            ConeSide sa;
-            const bool a_ok = cone_side(c0, float(A.x0x[j0]), float(A.x0y[j0]), float(A.x0z[j0]), A.eta0, sa);
-            keep = all || !a_ok || !b_ok || cone_meet(c1, cth, sth, sa, sb);
-        }
-        const unsigned long long bal = __ballot(keep);
-        if (lane == 0) {
-            s_bal[w][k] = bal;
-            if (w == 0) {
-                s_j0[k] = j0;
-                s_j2[k] = j2;
+            const unsigned long long bal = __ballot(keep);
+            if (lane == 0) {
+                s_bal[w][k] = bal;
+                if (w == 0) {
+                    s_j0[k] = j0;
+                    s_j2[k] = j2;
+                }
+            }
+            mine += keep ? 1 : 0;
+            if (++j2 == A.n2) {
+                j2 = 0;
+                ++j0;
             }
         }
-        mine += keep ? 1 : 0;
-        if (++j2 == A.n2) {
-            j2 = 0;
-            ++j0;
+        const int incl = wave_incl_scan(mine);
+        const int total = __shfl(incl, kWave - 1, kWave);
+        __syncthreads();   // ballots and pair indices visible to every lane
+        // exclusive per-pair prefix counts of this wave (4 pairs per lane)
+        {
+            constexpr int kPer = kCullPts / kWave;
+            int cnt[kPer], sum = 0;
+    #pragma unroll
+            for (int i = 0; i < kPer; ++i) {
+                const int k = lane * kPer + i;
+                cnt[i] = k < npairs ? __popcll(s_bal[w][k]) : 0;
+                sum += cnt[i];
+            }
+            int run = wave_incl_scan(sum) - sum;
+    #pragma unroll
+            for (int i = 0; i < kPer; ++i) {
+                s_cum[w][lane * kPer + i] = run;
+                run += cnt[i];
+            }
         }
-    }
-    const int incl = wave_incl_scan(mine);
-    const int total = __shfl(incl, kWave - 1, kWave);
-    __syncthreads();   // ballots and pair indices visible to every lane
-    // exclusive per-pair prefix counts of this wave (4 pairs per lane)
-    {
-        constexpr int kPer = kCullPts / kWave;
-        int cnt[kPer], sum = 0;
-#pragma unroll
-        for (int i = 0; i < kPer; ++i) {
-            const int k = lane * kPer + i;
-            cnt[i] = k < npairs ? __popcll(s_bal[w][k]) : 0;
-            sum += cnt[i];
+        const unsigned long long base = block_reserve((unsigned long long)total, A.out_count, s_slots);
+        for (int sidx = lane; sidx < total; sidx += kWave) {
+            // last pair k with s_cum[k] <= sidx
+            int lo = 0, hi = npairs - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_cum[w][mid] <= sidx) lo = mid;
+                else hi = mid - 1;
+            }
+            const int src = select_bit(s_bal[w][lo], sidx - s_cum[w][lo]);
+            const unsigned long long idx = base + (unsigned long long)sidx;
+            if (idx < (unsigned long long)A.cap) {
+                A.out_x0[idx] = s_j0[lo];
+                A.out_x2[idx] = s_j2[lo];
+                A.out_tri[idx] = t0 + w * kWave + src;
+            }
         }
-        int run = wave_incl_scan(sum) - sum;
-#pragma unroll
-        for (int i = 0; i < kPer; ++i) {
-            s_cum[w][lane * kPer + i] = run;
-            run += cnt[i];
-        }
-    }
-    const unsigned long long base = block_reserve((unsigned long long)total, A.out_count, s_slots);
-    for (int sidx = lane; sidx < total; sidx += kWave) {
-        // last pair k with s_cum[k] <= sidx
-        int lo = 0, hi = npairs - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (s_cum[w][mid] <= sidx) lo = mid;
-            else hi = mid - 1;
-        }
-        const int src = select_bit(s_bal[w][lo], sidx - s_cum[w][lo]);
-        const unsigned long long idx = base + (unsigned long long)sidx;
-        if (idx < (unsigned long long)A.cap) {
-            A.out_x0[idx] = s_j0[lo];
-            A.out_x2[idx] = s_j2[lo];
-            A.out_tri[idx] = t0 + w * kWave + src;
-        }
+        __syncthreads();   // LDS is reused by the next block of the stride
     }
 }
 
@@ -224,8 +229,8 @@ hipError_t launch_cull_1bounce(const CullArgs& A, hipStream_t stream)
     if (n_pairs <= 0 || A.n_tris <= 0) return hipSuccess;
     const int64_t npb = (n_pairs + kCullPts - 1) / kCullPts;
     const int64_t nblk = npb * ((A.n_tris + 255) / 256);
-    if (nblk > 2147483647LL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_cull_1bounce, dim3(unsigned(nblk)), dim3(256), 0, stream, A);
+    const int64_t grid = nblk < (int64_t(1) << 22) ? nblk : (int64_t(1) << 22);
+    hipLaunchKernelGGL(k_cull_1bounce, dim3(unsigned(grid)), dim3(256), 0, stream, A);
     return hipGetLastError();
 }
 

@@ -992,16 +992,19 @@ __global__ void __launch_bounds__(64) k_tt_solve(TTArgs A)
 {
     __shared__ double lds[kLdsDoubles];
     __shared__ TTGeo sgeo;
-    const int64_t q = blockIdx.x;
-    if (q >= A.nq) return;
-    tt_tuple(A, q, lds, &sgeo, 0);
+    // grid-stride over tuples: a launch may hold at most 2^32 work-items
+    for (int64_t q = blockIdx.x; q < A.nq; q += gridDim.x) {
+        tt_tuple(A, q, lds, &sgeo, 0);
+        __syncthreads();
+    }
 }
 
 hipError_t launch_tt_solve(const TTArgs& A, hipStream_t stream)
 {
     if (A.nq <= 0) return hipSuccess;
     if (A.nq > 2147483647LL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_tt_solve, dim3(unsigned(A.nq)), dim3(kWave), 0, stream, A);
+    const int64_t blocks = A.nq < (int64_t(1) << 22) ? A.nq : (int64_t(1) << 22);
+    hipLaunchKernelGGL(k_tt_solve, dim3(unsigned(blocks)), dim3(kWave), 0, stream, A);
     return hipGetLastError();
 }
 
