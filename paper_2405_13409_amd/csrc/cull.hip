@@ -55,10 +55,11 @@ __device__ __forceinline__ bool cone_side(float4 c0, float px, float py, float p
     const float rl = c0.w * 1.0001f;
     if (!(d2 > rl * rl)) return false;
     const float ia = __builtin_amdgcn_rsqf(d2);
-    const float sa = c0.w * ia * 1.000001f;
-    const float co = __builtin_amdgcn_sqrtf(fmaxf(0.0f, 1.0f - sa * sa));   // cos theta
-    // 2 sin(theta/2) = sqrt(2 (1 - cos theta)) = sin theta sqrt(2 / (1 + cos theta)), free of cancellation
-    const float chord = sa * __builtin_amdgcn_rsqf(0.5f * (1.0f + co)) * 1.000001f;
+    const float sa = fminf(c0.w * ia * 1.000001f, 1.0f);   // sin theta
+    // 2 sin(theta/2) = sin theta sqrt(2 / (1 + cos theta)), and sqrt(2 / (1 + sqrt(1 - s^2)))
+    // <= 1 + (sqrt 2 - 1) s^2 on [0,1] (convex in s^2, equal at both ends): an upper bound of
+    // the chord without square roots
+    const float chord = sa * fmaf(0.41422f, sa * sa, 1.0f) * 1.000001f;
     const float e = eta * ia;
     s.hx = e * ax;
     s.hy = e * ay;
@@ -119,6 +120,7 @@ __global__ void __launch_bounds__(256) k_cull_1bounce(CullArgs A)
     __shared__ unsigned long long s_bal[4][kCullPts];
     __shared__ int s_cum[4][kCullPts];
     __shared__ int s_j0[kCullPts], s_j2[kCullPts];
+    __shared__ float4 s_p0[kCullPts], s_p2[kCullPts];
     __shared__ unsigned long long s_slots[kMaxBlockWaves + 1];
     const int ntb = (A.n_tris + 255) / 256;
     const int64_t nblk = ((int64_t(A.n0) * A.n2 + kCullPts - 1) / kCullPts) * ntb;
@@ -142,7 +144,17 @@ __global__ void __launch_bounds__(256) k_cull_1bounce(CullArgs A)
         const int64_t n_pairs = int64_t(A.n0) * A.n2;
         const int64_t pair0 = pblock * kCullPts;
         const int npairs = int(min<int64_t>(kCullPts, n_pairs - pair0));
-        int j0 = int(pair0 / A.n2), j2 = int(pair0 % A.n2);
+        // stage the block's pairs (ids and float coordinates) in LDS: every
+        // lane reads the same pair, and a global load per pair would stall
+        for (int k = threadIdx.x; k < npairs; k += blockDim.x) {
+            const int64_t pr = pair0 + k;
+            const int jj0 = int(pr / A.n2), jj2 = int(pr % A.n2);
+            s_j0[k] = jj0;
+            s_j2[k] = jj2;
+            s_p0[k] = make_float4(float(A.x0x[jj0]), float(A.x0y[jj0]), float(A.x0z[jj0]), 0.0f);
+            s_p2[k] = make_float4(float(A.x2x[jj2]), float(A.x2y[jj2]), float(A.x2z[jj2]), 0.0f);
+        }
+        __syncthreads();
         int j2_side = -1;
         ConeSide sb{0.0f, 0.0f, 0.0f, 0.0f};
         bool b_ok = false;
@@ -150,27 +162,20 @@ __global__ void __launch_bounds__(256) k_cull_1bounce(CullArgs A)
         for (int k = 0; k < npairs; ++k) {
             bool keep = false;
             if (tri_ok) {
+                const int j2 = s_j2[k];
                 if (j2 != j2_side) {
-                    b_ok = cone_side(c0, float(A.x2x[j2]), float(A.x2y[j2]), float(A.x2z[j2]), A.eta1, sb);
+                    const float4 x2 = s_p2[k];
+                    b_ok = cone_side(c0, x2.x, x2.y, x2.z, A.eta1, sb);
                     j2_side = j2;
                 }
+                const float4 x0 = s_p0[k];
                 ConeSide sa;
-                const bool a_ok = cone_side(c0, float(A.x0x[j0]), float(A.x0y[j0]), float(A.x0z[j0]), A.eta0, sa);
+                const bool a_ok = cone_side(c0, x0.x, x0.y, x0.z, A.eta0, sa);
                 keep = all || !a_ok || !b_ok || cone_meet(c1, cth, sth, sa, sb);
             }
             const unsigned long long bal = __ballot(keep);
-            if (lane == 0) {
-                s_bal[w][k] = bal;
-                if (w == 0) {
-                    s_j0[k] = j0;
-                    s_j2[k] = j2;
-                }
-            }
+            if (lane == 0) s_bal[w][k] = bal;
             mine += keep ? 1 : 0;
-            if (++j2 == A.n2) {
-                j2 = 0;
-                ++j0;
-            }
         }
         const int incl = wave_incl_scan(mine);
         const int total = __shfl(incl, kWave - 1, kWave);
