@@ -10,6 +10,7 @@ namespace spoly {
 
 constexpr int kMaxLaneSol = 4;
 constexpr double kNearDoubleU = 1e-3;   // u-root pairs closer than this are tried from their midpoint
+constexpr double kRefineWindow = 0.005; // FP32 reflection: refine v when the nearest u misses the triangle by less
 
 struct Geo {            // FP64 geometry of one instance (after the edge relabelling)
     V3<double> p0, e1, e2, n0, dn1, dn2, x0, x2;
@@ -436,14 +437,13 @@ __device__ __forceinline__ double refine_v64(const Geo& g, double v)
 }
 
 // One root v of r: u from a(u)|v, FP64 polish, closed-triangle and path-space checks.
-template <int EV, int F>
-__device__ __forceinline__ void back_root(const Geo& g, const OneBounceArgs& A, const P2<double, 1 + F>& a64, double v,
-                                          LaneSols& S, int& ncand)
+// Real u roots of a(u)|v (ascending) from the FP64 coefficients; `near`
+// reports a complex pair within kRefineWindow of the real axis (the case a
+// slightly wrong v produces).
+template <int F>
+__device__ __forceinline__ int u_roots(const P2<double, 1 + F>& a64, double v, double (&us)[2], bool& near)
 {
     constexpr int TA = 1 + F;
-    if constexpr (EV == SPOLY_R) {
-        if (A.refine_v) v = refine_v64<F>(g, v);
-    }
     double c[TA + 1];
 #pragma unroll
     for (int i = 0; i <= TA; ++i) {
@@ -452,19 +452,21 @@ __device__ __forceinline__ void back_root(const Geo& g, const OneBounceArgs& A, 
         for (int j = TA - i; j >= 0; --j) s = fma(s, v, a64.c[tri_idx(TA, i, j)]);
         c[i] = s;
     }
-    double us[2] = {0.0, 0.0};
-    int nu = 0;
+    us[0] = us[1] = 0.0;
+    near = false;
     if constexpr (TA == 2) {
-        double qa = c[2], qb = c[1], qc = c[0];
+        const double qa = c[2], qb = c[1], qc = c[0];
         if (qa != 0.0) {
-            double disc = qb * qb - 4.0 * qa * qc;
+            const double disc = qb * qb - 4.0 * qa * qc;
             if (disc > 0.0) {
-                double qq = -0.5 * (qb + copysign(sqrt(disc), qb));
-                double r1 = qq / qa, r2 = qc / qq;
+                const double qq = -0.5 * (qb + copysign(sqrt(disc), qb));
+                const double r1 = qq / qa, r2 = qc / qq;
                 us[0] = fmin(r1, r2);
                 us[1] = fmax(r1, r2);
-                nu = 2;
-            } else if (-disc <= kNearDoubleU * kNearDoubleU * qa * qa) {
+                return 2;
+            }
+            near = -disc <= 4.0 * kRefineWindow * kRefineWindow * qa * qa;
+            if (-disc <= kNearDoubleU * kNearDoubleU * qa * qa) {
                 // The two u roots are within kNearDoubleU of each other or a
                 // complex pair that close to the real axis: v is known only to
                 // the isolation tolerance, so a solution with a near-double u
@@ -472,16 +474,49 @@ __device__ __forceinline__ void back_root(const Geo& g, const OneBounceArgs& A, 
                 // is the start point; the FP64 polish (whose Jacobian does not
                 // vanish there at a simple solution) and validation decide.
                 us[0] = -qb / (2.0 * qa);
-                nu = 1;
+                return 1;
             }
-        } else if (qb != 0.0) {
-            us[0] = -qc / qb;
-            nu = 1;
+            return 0;
         }
+        if (qb != 0.0) {
+            us[0] = -qc / qb;
+            return 1;
+        }
+        return 0;
     } else {
         if (c[1] != 0.0) {
             us[0] = -c[0] / c[1];
-            nu = 1;
+            return 1;
+        }
+        return 0;
+    }
+}
+
+// With kDefer the FP64 refinement of v is not done here: the root is reported
+// (return false, nothing emitted) so that the caller can hand its candidate to
+// the FP64 solve instead.
+template <int EV, int F, bool kDefer = false>
+__device__ __forceinline__ bool back_root(const Geo& g, const OneBounceArgs& A, const P2<double, 1 + F>& a64, double v,
+                                          LaneSols& S, int& ncand)
+{
+    double us[2];
+    bool near = false;
+    int nu = u_roots<F>(a64, v, us, near);
+    if constexpr (EV == SPOLY_R) {
+        // FP32 roots: when no u lands in the triangle but one is close (or
+        // the pair is nearly real), v may be the culprit: refine it in FP64
+        // and solve for u again.
+        if (A.refine_v) {
+            bool in = false, close = near;
+            for (int m = 0; m < nu; ++m) {
+                in = in || (us[m] >= -A.u_margin && us[m] <= 1.0 - v + A.u_margin);
+                close = close || (us[m] >= -kRefineWindow && us[m] <= 1.0 + kRefineWindow - v);
+            }
+            if (!in && close) {
+                if constexpr (kDefer) return false;
+                v = refine_v64<F>(g, v);
+                nu = u_roots<F>(a64, v, us, near);
+            }
         }
     }
 #pragma unroll
@@ -501,6 +536,7 @@ __device__ __forceinline__ void back_root(const Geo& g, const OneBounceArgs& A, 
         double edge = fmin(fmin(u, vv), w);
         push_sol(S, u, vv, res, edge, A.dedup);
     }
+    return true;
 }
 
 template <typename R, int EV, int F>
@@ -881,7 +917,7 @@ __global__ void __launch_bounds__(256) k_ob_back(OneBounceArgs A)
         LaneSols S;
         S.n = 0;
         int ncand = 0, tid = -1;
-        bool swapped = false;
+        bool swapped = false, defer = false;
         int64_t q = 0;
         if (active) {
             q = A.items_q[i];
@@ -889,13 +925,30 @@ __global__ void __launch_bounds__(256) k_ob_back(OneBounceArgs A)
             Geo g;
             tid = setup_geo<EV>(A, q, g);
             swapped = g.swapped;
+            bool ok = true;
             if (g.flat) {
                 const P2<double, 1> a64 = a_fp64<0>(g);
-                for (int j = 0; j < nr; ++j) back_root<EV, 0>(g, A, a64, A.items_v[kObEmit * i + j], S, ncand);
+                for (int j = 0; j < nr && ok; ++j)
+                    ok = back_root<EV, 0, true>(g, A, a64, A.items_v[kObEmit * i + j], S, ncand);
             } else {
                 const P2<double, 2> a64 = a_fp64<1>(g);
-                for (int j = 0; j < nr; ++j) back_root<EV, 1>(g, A, a64, A.items_v[kObEmit * i + j], S, ncand);
+                for (int j = 0; j < nr && ok; ++j)
+                    ok = back_root<EV, 1, true>(g, A, a64, A.items_v[kObEmit * i + j], S, ncand);
             }
+            if (!ok) {
+                // An FP32 root whose u misses the triangle narrowly: the whole
+                // candidate goes to the FP64 solve of the full list, so that
+                // the waves here do not wait for the refinement of few lanes.
+                defer = true;
+                S.n = 0;
+                ncand = 0;
+            }
+        }
+        if (A.refine_v) {
+            const int wf = defer ? 1 : 0, fi = wave_incl_scan(wf);
+            const unsigned long long bf = block_reserve((unsigned long long)__shfl(fi, kWave - 1, kWave),
+                                                        A.items_count + 1, s_slots);
+            if (defer) A.full_q[bf + (unsigned long long)(fi - wf)] = int32_t(q);
         }
         emit_lane(A, q, active, 0, tid, swapped, S, 0, ncand, 0, s_slots, false);
     }
@@ -942,7 +995,7 @@ hipError_t launch_onebounce_2phase(const OneBounceArgs& A, int ev, int prec, int
     hipLaunchKernelGGL(k_zero_items, dim3(1), dim3(1), 0, stream, A.items_count);
     const dim3 block(256), grid(unsigned((A.nq + 255) / 256));
     const dim3 bgrid(unsigned(back_blocks > 0 ? back_blocks : 1));
-    const dim3 fgrid(unsigned(back_blocks > 0 ? (back_blocks + 7) / 8 : 1));
+    const dim3 fgrid(bgrid);   // the full list can be long (deferred FP32 roots): fill the chip
     // Refraction always runs in FP64 (see launch_onebounce).
     if (ev == SPOLY_R && prec == SPOLY_FP64) {
         hipLaunchKernelGGL((k_ob_front<double, SPOLY_R>), grid, block, 0, stream, A);
