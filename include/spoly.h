@@ -167,7 +167,9 @@ spoly_status spoly_cull_1bounce(spoly_ctx *ctx, const spoly_mesh *mesh,
  * for refraction 112 more; grown on demand, and growing synchronises the
  * device); the back solves, polishes and validates the listed candidates.  Calls that share a
  * context must therefore be issued on one stream.  E_DEVICE if the workspace
- * cannot be allocated.
+ * cannot be allocated.  With SPOLY_FP32_POLISH64, candidates with more than two
+ * roots, or with a float root whose u misses the triangle by less than 0.005,
+ * are solved again from scratch in double precision.
  */
 spoly_status spoly_solve_1bounce(spoly_ctx *ctx, const spoly_mesh *mesh,
                                  const spoly_points *x0s, const spoly_points *x2s,

@@ -16,7 +16,7 @@ struct OneBounceArgs {
     double eta0, eta1;
     double iso_eps, tau, u_margin, dedup;
     int32_t polish_iters;
-    int32_t refine_v;             // refine each root v of r in FP64 before the u solve (FP32 reflection)
+    int32_t refine_v;             // FP32 reflection: a root whose u narrowly misses the triangle is refined in FP64 (fused) or deferred to the FP64 full list (two-phase)
     spoly_solution* out;
     int64_t cap;
     unsigned long long* out_count;
