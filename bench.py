@@ -31,9 +31,9 @@ PEAK_HBM = 8000.0   # GB/s
 # workload, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch), scaled by what the same
 # counters read for a plain 256 MiB device copy (FETCH x2.0, WRITE x1.0).  Valid only for the kernel
 # sources they were taken on (sha256 prefix over the files in _KERNEL_SOURCES); otherwise traffic is null.
-TRAFFIC_R = {"sha": "32bc90d5c4e0562b", "candidates": 99118927,
-             "fetch_kib": 619429.38 + 813770.63 + 280.16, "write_kib": 664015.81 + 488060.03 + 10.41,
-             "fetch_scale": 262144.0 / 131084.48, "write_scale": 262144.0 / 262144.0}
+TRAFFIC_R = {"sha": "88853147065c37ac", "candidates": 99118927,
+             "fetch_kib": 619105.6 + 810954.9 + 38204.0, "write_kib": 664046.5 + 493018.4 + 42.1,
+             "fetch_scale": 262144.0 / 131084.5, "write_scale": 262144.0 / 262144.0}
 _KERNEL_SOURCES = ("onebounce.hip", "spoly_dev.hpp", "laplace_gen.inc", "onebounce.hpp")
 
 
