@@ -37,7 +37,7 @@ __global__ void __launch_bounds__(256) k_tri_cones(const double* px, const doubl
     cone[2 * t + 1] = make_float4(float(an.x), float(an.y), float(an.z), float(th + 1e-6));
 }
 
-constexpr int kCullPts = 256;  // (x0, x2) pairs per thread; one atomic per block of 256 x 256 tests
+constexpr int kCullPts = 256;  // (x0, x2) pairs per tile; each listed triangle is tested against all of them
 
 // One side of the half-vector bound: the unit direction from the triangle's
 // bounding sphere (centre c, radius rad) towards point p, scaled by eta, and
@@ -106,45 +106,121 @@ __device__ __forceinline__ int select_bit(unsigned long long m, int r)
     return pos;
 }
 
-// Grid: (pair block) x (triangle block of 256).  Each thread tests one
-// triangle against kCullPts consecutive (x0, x2) pairs, keeping the wave's
-// per-pair ballots in LDS.  The block reserves its whole output range with
-// one atomic (a single counter shared by every block is the bottleneck when
-// each wave reserves on its own).  Each wave then writes its kept triples in
-// (pair, lane) order with full-width stores: output slot s of the wave is
-// mapped back to its pair by a binary search over the per-pair prefix counts
-// and to its lane by selecting the right bit of that pair's ballot.  The x2
-// side of the bound is recomputed only when x2 changes (with one light: once).
+// Bounding sphere of a tile's points: centre = mean of the n staged points,
+// radius = max distance to it (rounded outward).  Block-wide; every thread calls.
+__device__ __forceinline__ float4 tile_sphere(const float4* s_p, int n, float* s_red)
+{
+    const int w = threadIdx.x / kWave, nw = (blockDim.x + kWave - 1) / kWave;
+    float x = 0.0f, y = 0.0f, z = 0.0f;
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+        x += s_p[k].x;
+        y += s_p[k].y;
+        z += s_p[k].z;
+    }
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) {
+        x += __shfl_xor(x, d, kWave);
+        y += __shfl_xor(y, d, kWave);
+        z += __shfl_xor(z, d, kWave);
+    }
+    if (lane_id() == 0) {
+        s_red[3 * w] = x;
+        s_red[3 * w + 1] = y;
+        s_red[3 * w + 2] = z;
+    }
+    __syncthreads();
+    x = y = z = 0.0f;
+    for (int i = 0; i < nw; ++i) {
+        x += s_red[3 * i];
+        y += s_red[3 * i + 1];
+        z += s_red[3 * i + 2];
+    }
+    const float inv = 1.0f / float(n > 0 ? n : 1);
+    x *= inv;
+    y *= inv;
+    z *= inv;
+    float r2 = 0.0f;
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+        const float dx = s_p[k].x - x, dy = s_p[k].y - y, dz = s_p[k].z - z;
+        r2 = fmaxf(r2, dx * dx + dy * dy + dz * dz);
+    }
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) r2 = fmaxf(r2, __shfl_xor(r2, d, kWave));
+    __syncthreads();   // the sums above have been read
+    if (lane_id() == 0) s_red[w] = r2;
+    __syncthreads();
+    r2 = 0.0f;
+    for (int i = 0; i < nw; ++i) r2 = fmaxf(r2, s_red[i]);
+    __syncthreads();   // s_red may be reused after this call
+    return make_float4(x, y, z, __builtin_amdgcn_sqrtf(r2) * 1.0001f + 1e-6f);
+}
+
+// One side of the tile bound: the unit direction from the triangle's centre c
+// to the tile's centre p, and eta times an upper bound of the angle of the cone
+// of directions from the triangle's sphere (radius rad) to the tile's sphere
+// (radius rho), asin((rad + rho) / |p - c|) <= s (1 + (pi/2 - 1) s^2) on [0,1]
+// (asin(s)/s is convex in s^2 and equal to it at both ends).  The angle, not
+// the chord, is what makes the bound hold for every pair of the tile: for a
+// point x of the tile, the pair's own direction differs from the tile's by at
+// most (angle - pair's angle), and chord <= angle.
+__device__ __forceinline__ bool tile_side(float4 c0, float4 p, float eta, ConeSide& s)
+{
+    const float ax = p.x - c0.x, ay = p.y - c0.y, az = p.z - c0.z;
+    const float d2 = ax * ax + ay * ay + az * az;
+    const float rl = (c0.w + p.w) * 1.0001f;
+    if (!(d2 > rl * rl)) return false;
+    const float ia = __builtin_amdgcn_rsqf(d2);
+    const float sa = (c0.w + p.w) * ia * 1.000001f;
+    if (!(sa < 1.0f)) return false;
+    const float e = eta * ia;
+    s.hx = e * ax;
+    s.hy = e * ay;
+    s.hz = e * az;
+    s.dch = eta * sa * fmaf(0.5708f, sa * sa, 1.0f) * 1.001f;
+    return true;
+}
+
+constexpr int kCullTriRange = 4096;   // triangles per block, tile-tested 256 at a time
+
+// Two-level cull.  Grid-stride over (tile, triangle range): a tile is kCullPts
+// consecutive (x0, x2) pairs, staged in LDS with the bounding spheres of its x0
+// and x2 points.  Each triangle of the range is first tested against the whole
+// tile (the cone of directions from the triangle to the tile's spheres contains
+// every pair's cone, with an outward-rounded angle bound, so a tile rejection
+// implies the rejection of each of its pairs); the triangles that pass are
+// compacted into an LDS list in triangle order, and each full list of 256 (and
+// the rest at the end of the range) is tested pair by pair exactly as a flat
+// cull would: one thread per listed triangle, looping over the tile's pairs
+// and keeping a 256-bit mask of the kept ones.  The block reserves its output
+// range with one atomic; each wave then writes its kept triples in (lane,
+// pair) order with full-width stores, mapping output slot s back to its lane
+// by a binary search over the per-lane prefix counts and to its pair by
+// selecting the right bit of that lane's mask.  Triangle-major output keeps
+// the candidates of one wave of the solve similar (one triangle, neighbouring
+// points).  Points that are close in index should be close in space (pixel
+// tiles, a Morton order) for the tile test to reject.
 __global__ void __launch_bounds__(256) k_cull_1bounce(CullArgs A)
 {
-    __shared__ unsigned long long s_bal[4][kCullPts];
-    __shared__ int s_cum[4][kCullPts];
+    __shared__ unsigned long long s_msk[4][kWave][kCullPts / kWave];
+    __shared__ int s_lc[4][kWave];
     __shared__ int s_j0[kCullPts], s_j2[kCullPts];
     __shared__ float4 s_p0[kCullPts], s_p2[kCullPts];
+    __shared__ int s_list[2 * 256];
+    __shared__ int s_wc[kMaxBlockWaves];
+    __shared__ float s_red[3 * kMaxBlockWaves];
     __shared__ unsigned long long s_slots[kMaxBlockWaves + 1];
-    const int ntb = (A.n_tris + 255) / 256;
-    const int64_t nblk = ((int64_t(A.n0) * A.n2 + kCullPts - 1) / kCullPts) * ntb;
-    // grid-stride over (pair block, triangle block): a launch may hold at most 2^32 work-items
+    const int ntr = (A.n_tris + kCullTriRange - 1) / kCullTriRange;
+    const int64_t n_pairs = int64_t(A.n0) * A.n2;
+    const int64_t nblk = ((n_pairs + kCullPts - 1) / kCullPts) * ntr;
+    const int w = threadIdx.x / kWave;
+    const int lane = lane_id();
+    const int nw = blockDim.x / kWave;
     for (int64_t vb = blockIdx.x; vb < nblk; vb += gridDim.x) {
-        const int t0 = int(vb % ntb) * blockDim.x;
-        const int t = t0 + threadIdx.x;
-        const int64_t pblock = vb / ntb;
-        const bool tri_ok = t < A.n_tris;
-        const int w = threadIdx.x / kWave;
-        const int lane = lane_id();
-        float4 c0 = make_float4(0, 0, 0, 0), c1 = make_float4(0, 0, 0, 4.0f);
-        if (tri_ok) {
-            c0 = A.tri_cone[2 * t];
-            c1 = A.tri_cone[2 * t + 1];
-        }
-        // a normal cone of 90 degrees or more (with the margin) meets every h
-        const float thm = c1.w + A.margin;
-        const bool all = !(thm < 1.5707f);
-        const float cth = cosf(fminf(thm, 1.5707f)), sth = sinf(fminf(thm, 1.5707f));
-        const int64_t n_pairs = int64_t(A.n0) * A.n2;
-        const int64_t pair0 = pblock * kCullPts;
+        const int tr0 = int(vb % ntr) * kCullTriRange;
+        const int tr1 = min(A.n_tris, tr0 + kCullTriRange);
+        const int64_t pair0 = (vb / ntr) * kCullPts;
         const int npairs = int(min<int64_t>(kCullPts, n_pairs - pair0));
-        // stage the block's pairs (ids and float coordinates) in LDS: every
+        // stage the tile's pairs (ids and float coordinates) in LDS: every
         // lane reads the same pair, and a global load per pair would stall
         for (int k = threadIdx.x; k < npairs; k += blockDim.x) {
             const int64_t pr = pair0 + k;
@@ -155,66 +231,126 @@ __global__ void __launch_bounds__(256) k_cull_1bounce(CullArgs A)
             s_p2[k] = make_float4(float(A.x2x[jj2]), float(A.x2y[jj2]), float(A.x2z[jj2]), 0.0f);
         }
         __syncthreads();
-        int j2_side = -1;
-        ConeSide sb{0.0f, 0.0f, 0.0f, 0.0f};
-        bool b_ok = false;
-        int mine = 0;
-        for (int k = 0; k < npairs; ++k) {
-            bool keep = false;
-            if (tri_ok) {
-                const int j2 = s_j2[k];
-                if (j2 != j2_side) {
-                    const float4 x2 = s_p2[k];
-                    b_ok = cone_side(c0, x2.x, x2.y, x2.z, A.eta1, sb);
-                    j2_side = j2;
+        const float4 sph0 = tile_sphere(s_p0, npairs, s_red);
+        const float4 sph2 = tile_sphere(s_p2, npairs, s_red);
+        int nlist = 0;
+        for (int tc = tr0; tc < tr1; tc += blockDim.x) {
+            // tile test of triangles tc .. tc+255; passing ids appended in order
+            const int t = tc + threadIdx.x;
+            bool pass = false;
+            if (t < tr1) {
+                const float4 c0 = A.tri_cone[2 * t], c1 = A.tri_cone[2 * t + 1];
+                const float thm = c1.w + A.margin;
+                pass = !(thm < 1.5707f);
+                if (!pass) {
+                    ConeSide sa, sb;
+                    pass = !tile_side(c0, sph0, A.eta0, sa) || !tile_side(c0, sph2, A.eta1, sb) ||
+                           cone_meet(c1, cosf(thm), sinf(thm), sa, sb);
                 }
-                const float4 x0 = s_p0[k];
-                ConeSide sa;
-                const bool a_ok = cone_side(c0, x0.x, x0.y, x0.z, A.eta0, sa);
-                keep = all || !a_ok || !b_ok || cone_meet(c1, cth, sth, sa, sb);
             }
-            const unsigned long long bal = __ballot(keep);
-            if (lane == 0) s_bal[w][k] = bal;
-            mine += keep ? 1 : 0;
+            const unsigned long long bal = __ballot(pass);
+            if (lane == 0) s_wc[w] = __popcll(bal);
+            __syncthreads();
+            int off = nlist;
+            for (int i = 0; i < w; ++i) off += s_wc[i];
+            int added = 0;
+            for (int i = 0; i < nw; ++i) added += s_wc[i];
+            if (pass) off += __popcll(bal & ((1ull << lane) - 1ull));
+            if (pass) s_list[off] = t;
+            nlist += added;
+            __syncthreads();
+            const bool last = tc + int(blockDim.x) >= tr1;
+            // pair-by-pair test of the first min(256, nlist) listed triangles,
+            // while a full list is ready (or, at the end of the range, any)
+            while (nlist >= int(blockDim.x) || (last && nlist > 0)) {
+                const int nf = min(nlist, int(blockDim.x));
+                const bool wave_on = w * kWave < nf;
+                const bool tri_ok = int(threadIdx.x) < nf;
+                int mine = 0;
+                unsigned long long m[kCullPts / kWave];   // pairs kept for this lane's triangle
+#pragma unroll
+                for (int kw = 0; kw < kCullPts / kWave; ++kw) m[kw] = 0ull;
+                if (wave_on) {
+                    float4 c0 = make_float4(0, 0, 0, 0), c1 = make_float4(0, 0, 0, 4.0f);
+                    if (tri_ok) {
+                        const int tt = s_list[threadIdx.x];
+                        c0 = A.tri_cone[2 * tt];
+                        c1 = A.tri_cone[2 * tt + 1];
+                    }
+                    // a normal cone of 90 degrees or more (with the margin) meets every h
+                    const float thm = c1.w + A.margin;
+                    const bool all = !(thm < 1.5707f);
+                    const float cth = cosf(fminf(thm, 1.5707f)), sth = sinf(fminf(thm, 1.5707f));
+                    int j2_side = -1;
+                    ConeSide sb{0.0f, 0.0f, 0.0f, 0.0f};
+                    bool b_ok = false;
+#pragma unroll
+                    for (int kw = 0; kw < kCullPts / kWave; ++kw) {
+                        const int kend = min(npairs - kw * kWave, kWave);
+                        unsigned long long mk = 0ull;
+                        for (int b = 0; b < kend; ++b) {
+                            const int k = kw * kWave + b;
+                            bool keep = false;
+                            if (tri_ok) {
+                                const int j2 = s_j2[k];
+                                if (j2 != j2_side) {
+                                    const float4 x2 = s_p2[k];
+                                    b_ok = cone_side(c0, x2.x, x2.y, x2.z, A.eta1, sb);
+                                    j2_side = j2;
+                                }
+                                const float4 x0 = s_p0[k];
+                                ConeSide sa;
+                                const bool a_ok = cone_side(c0, x0.x, x0.y, x0.z, A.eta0, sa);
+                                keep = all || !a_ok || !b_ok || cone_meet(c1, cth, sth, sa, sb);
+                            }
+                            mk |= (unsigned long long)(keep ? 1u : 0u) << b;
+                        }
+                        m[kw] = mk;
+                        mine += __popcll(mk);
+                    }
+                }
+                const int incl = wave_incl_scan(mine);
+                const int total = __shfl(incl, kWave - 1, kWave);
+                if (wave_on) {
+                    s_lc[w][lane] = incl - mine;
+#pragma unroll
+                    for (int kw = 0; kw < kCullPts / kWave; ++kw) s_msk[w][lane][kw] = m[kw];
+                }
+                // (block_reserve synchronises the block: the masks are visible after it)
+                const unsigned long long base = block_reserve((unsigned long long)total, A.out_count, s_slots);
+                for (int sidx = lane; sidx < total; sidx += kWave) {
+                    // last lane L with s_lc[L] <= sidx, then the pair of that lane's r-th kept bit
+                    int lo = 0, hi = kWave - 1;
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (s_lc[w][mid] <= sidx) lo = mid;
+                        else hi = mid - 1;
+                    }
+                    int r = sidx - s_lc[w][lo], kw = 0;
+                    unsigned long long mk = s_msk[w][lo][0];
+                    while (r >= __popcll(mk)) {
+                        r -= __popcll(mk);
+                        mk = s_msk[w][lo][++kw];
+                    }
+                    const int k = kw * kWave + select_bit(mk, r);
+                    const unsigned long long idx = base + (unsigned long long)sidx;
+                    if (idx < (unsigned long long)A.cap) {
+                        A.out_x0[idx] = s_j0[k];
+                        A.out_x2[idx] = s_j2[k];
+                        A.out_tri[idx] = s_list[w * kWave + lo];
+                    }
+                }
+                __syncthreads();   // the processed list entries and masks are no longer read
+                // move the remaining listed triangles to the front
+                const int rest = nlist - nf;
+                int carry = -1;
+                if (int(threadIdx.x) < rest) carry = s_list[nf + threadIdx.x];
+                __syncthreads();
+                if (carry >= 0) s_list[threadIdx.x] = carry;
+                nlist = rest;
+                __syncthreads();
+            }
         }
-        const int incl = wave_incl_scan(mine);
-        const int total = __shfl(incl, kWave - 1, kWave);
-        __syncthreads();   // ballots and pair indices visible to every lane
-        // exclusive per-pair prefix counts of this wave (4 pairs per lane)
-        {
-            constexpr int kPer = kCullPts / kWave;
-            int cnt[kPer], sum = 0;
-    #pragma unroll
-            for (int i = 0; i < kPer; ++i) {
-                const int k = lane * kPer + i;
-                cnt[i] = k < npairs ? __popcll(s_bal[w][k]) : 0;
-                sum += cnt[i];
-            }
-            int run = wave_incl_scan(sum) - sum;
-    #pragma unroll
-            for (int i = 0; i < kPer; ++i) {
-                s_cum[w][lane * kPer + i] = run;
-                run += cnt[i];
-            }
-        }
-        const unsigned long long base = block_reserve((unsigned long long)total, A.out_count, s_slots);
-        for (int sidx = lane; sidx < total; sidx += kWave) {
-            // last pair k with s_cum[k] <= sidx
-            int lo = 0, hi = npairs - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (s_cum[w][mid] <= sidx) lo = mid;
-                else hi = mid - 1;
-            }
-            const int src = select_bit(s_bal[w][lo], sidx - s_cum[w][lo]);
-            const unsigned long long idx = base + (unsigned long long)sidx;
-            if (idx < (unsigned long long)A.cap) {
-                A.out_x0[idx] = s_j0[lo];
-                A.out_x2[idx] = s_j2[lo];
-                A.out_tri[idx] = t0 + w * kWave + src;
-            }
-        }
-        __syncthreads();   // LDS is reused by the next block of the stride
     }
 }
 
@@ -233,7 +369,7 @@ hipError_t launch_cull_1bounce(const CullArgs& A, hipStream_t stream)
     const int64_t n_pairs = int64_t(A.n0) * A.n2;
     if (n_pairs <= 0 || A.n_tris <= 0) return hipSuccess;
     const int64_t npb = (n_pairs + kCullPts - 1) / kCullPts;
-    const int64_t nblk = npb * ((A.n_tris + 255) / 256);
+    const int64_t nblk = npb * ((A.n_tris + kCullTriRange - 1) / kCullTriRange);
     const int64_t grid = nblk < (int64_t(1) << 22) ? nblk : (int64_t(1) << 22);
     hipLaunchKernelGGL(k_cull_1bounce, dim3(unsigned(grid)), dim3(256), 0, stream, A);
     return hipGetLastError();

@@ -131,11 +131,21 @@ def points_uniform(n: int, lo: float, hi: float, z: float, seed: int) -> np.ndar
     return np.concatenate([xy, np.full((n, 1), z)], axis=1)
 
 
-def points_grid(n: int, lo: float, hi: float, z: float) -> np.ndarray:
-    """n x n cell-centre grid on [lo,hi]^2 at height z (row-major in y, then x)."""
+def points_grid(n: int, lo: float, hi: float, z: float, tile: int = 1) -> np.ndarray:
+    """n x n cell-centre grid on [lo,hi]^2 at height z.  tile = 1: row-major in
+    y, then x.  tile = k (dividing n): k x k pixel tiles in row-major order,
+    each row-major inside, so that consecutive points are close in space."""
     g = lo + (np.arange(n) + 0.5) * (hi - lo) / n
     X, Y = np.meshgrid(g, g, indexing="xy")
-    return np.stack([X.ravel(), Y.ravel(), np.full(X.size, z)], axis=1)
+    P = np.stack([X.ravel(), Y.ravel(), np.full(X.size, z)], axis=1)
+    if tile <= 1:
+        return P
+    if n % tile:
+        raise ValueError(f"tile {tile} does not divide {n}")
+    nt = n // tile
+    # index [ty, tx, iy, ix] -> row-major pixel (ty*tile+iy, tx*tile+ix)
+    ty, tx, iy, ix = np.meshgrid(np.arange(nt), np.arange(nt), np.arange(tile), np.arange(tile), indexing="ij")
+    return P[((ty * tile + iy) * n + tx * tile + ix).ravel()]
 
 
 @dataclasses.dataclass
@@ -176,9 +186,10 @@ def glints_large_mesh(seed: int = 2) -> Mesh:
 
 
 def glints_large_points(event: str, res: int = 256) -> np.ndarray:
-    """res x res pixel-centre shading points on [-1,1]^2; z = 2 for reflection,
-    z = -2 (below the interface) for refraction."""
-    return points_grid(res, -1.0, 1.0, 2.0 if event == "R" else -2.0)
+    """res x res pixel-centre shading points on [-1,1]^2 in 16 x 16 pixel
+    tiles (when 16 divides res); z = 2 for reflection, z = -2 (below the
+    interface) for refraction."""
+    return points_grid(res, -1.0, 1.0, 2.0 if event == "R" else -2.0, 16 if res % 16 == 0 else 1)
 
 
 GLINTS_LARGE_LIGHT = np.asarray([[0.0, 0.0, 4.0]])
