@@ -742,9 +742,9 @@ __device__ __forceinline__ void emit_items(const OneBounceArgs& A, int64_t q, bo
 }
 
 // Fused front (reflection): coefficients, elimination and isolation in one
-// kernel of 86 VGPRs (five waves per SIMD), one candidate per lane.
+// kernel, one candidate per lane.
 template <typename R, int EV>
-__global__ void __launch_bounds__(256) k_ob_front(OneBounceArgs A)
+__device__ __forceinline__ void ob_front_body(const OneBounceArgs& A)
 {
     __shared__ unsigned long long s_slots[kMaxBlockWaves + 1];
     const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -763,6 +763,21 @@ __global__ void __launch_bounds__(256) k_ob_front(OneBounceArgs A)
         else nvr = front_collect<R, EV, 1>(g, A, vr, degen, uncertain);
     }
     emit_items(A, q, active, nvr, degen, vr, s_slots, uncertain);
+}
+
+template <typename R, int EV>
+__global__ void __launch_bounds__(256) k_ob_front(OneBounceArgs A)
+{
+    ob_front_body<R, EV>(A);
+}
+
+// FP32: six waves per SIMD (80 VGPRs and a few bytes of spill) run faster than
+// the five the compiler picks by itself (86 VGPRs); the FP64 instance would
+// spill heavily at that target and keeps its own allocation.
+template <>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) k_ob_front<float, SPOLY_R>(OneBounceArgs A)
+{
+    ob_front_body<float, SPOLY_R>(A);
 }
 
 // Front phase in two kernels (refraction).  k_ob_coef builds r(v) for every candidate and
