@@ -87,25 +87,6 @@ __device__ __forceinline__ bool cone_meet(float4 c1, float cth, float sth, const
     return cdot >= clim * (1.0f - 4e-6f);
 }
 
-// Position of the r-th set bit (r counted from 0) of a 64-bit mask.
-__device__ __forceinline__ int select_bit(unsigned long long m, int r)
-{
-    int pos = 0;
-    int c = __popc(unsigned(m));
-    if (r >= c) { r -= c; m >>= 32; pos += 32; }
-    unsigned x = unsigned(m);
-    c = __popc(x & 0xffffu);
-    if (r >= c) { r -= c; x >>= 16; pos += 16; }
-    c = __popc(x & 0xffu);
-    if (r >= c) { r -= c; x >>= 8; pos += 8; }
-    c = __popc(x & 0xfu);
-    if (r >= c) { r -= c; x >>= 4; pos += 4; }
-    c = __popc(x & 0x3u);
-    if (r >= c) { r -= c; x >>= 2; pos += 2; }
-    if (r >= int(x & 1u)) pos += 1;
-    return pos;
-}
-
 // Bounding sphere of a tile's points: centre = mean of the n staged points,
 // radius = max distance to it (rounded outward).  Block-wide; every thread calls.
 __device__ __forceinline__ float4 tile_sphere(const float4* s_p, int n, float* s_red)
@@ -180,7 +161,7 @@ __device__ __forceinline__ bool tile_side(float4 c0, float4 p, float eta, ConeSi
     return true;
 }
 
-constexpr int kCullTriRange = 4096;   // triangles per block, tile-tested 256 at a time
+constexpr int kCullTriRange = 4096;   // triangles per block (at most 32 x 256: one mask bit per chunk)
 
 // Two-level cull.  Grid-stride over (tile, triangle range): a tile is kCullPts
 // consecutive (x0, x2) pairs, staged in LDS with the bounding spheres of its x0
@@ -193,16 +174,13 @@ constexpr int kCullTriRange = 4096;   // triangles per block, tile-tested 256 at
 // cull would: one thread per listed triangle, looping over the tile's pairs
 // and keeping a 256-bit mask of the kept ones.  The block reserves its output
 // range with one atomic; each wave then writes its kept triples in (lane,
-// pair) order with full-width stores, mapping output slot s back to its lane
-// by a binary search over the per-lane prefix counts and to its pair by
-// selecting the right bit of that lane's mask.  Triangle-major output keeps
+// pair) order, lane by lane, the whole wave storing one lane's mask word at a
+// time to consecutive slots.  Triangle-major output keeps
 // the candidates of one wave of the solve similar (one triangle, neighbouring
 // points).  Points that are close in index should be close in space (pixel
 // tiles, a Morton order) for the tile test to reject.
 __global__ void __launch_bounds__(256) k_cull_1bounce(CullArgs A)
 {
-    __shared__ unsigned long long s_msk[4][kWave][kCullPts / kWave];
-    __shared__ int s_lc[4][kWave];
     __shared__ int s_j0[kCullPts], s_j2[kCullPts];
     __shared__ float4 s_p0[kCullPts], s_p2[kCullPts];
     __shared__ int s_list[2 * 256];
@@ -233,21 +211,29 @@ __global__ void __launch_bounds__(256) k_cull_1bounce(CullArgs A)
         __syncthreads();
         const float4 sph0 = tile_sphere(s_p0, npairs, s_red);
         const float4 sph2 = tile_sphere(s_p2, npairs, s_red);
-        int nlist = 0;
-        for (int tc = tr0; tc < tr1; tc += blockDim.x) {
-            // tile test of triangles tc .. tc+255; passing ids appended in order
-            const int t = tc + threadIdx.x;
-            bool pass = false;
+        // tile test of the whole range first (bit c: triangle tr0 + 256 c + thread),
+        // with no barrier between the loads, then compaction chunk by chunk
+        unsigned pmask = 0u;
+#pragma unroll 4
+        for (int c = 0; c < kCullTriRange / 256; ++c) {
+            const int t = tr0 + c * 256 + int(threadIdx.x);
             if (t < tr1) {
                 const float4 c0 = A.tri_cone[2 * t], c1 = A.tri_cone[2 * t + 1];
                 const float thm = c1.w + A.margin;
-                pass = !(thm < 1.5707f);
+                bool pass = !(thm < 1.5707f);
                 if (!pass) {
                     ConeSide sa, sb;
                     pass = !tile_side(c0, sph0, A.eta0, sa) || !tile_side(c0, sph2, A.eta1, sb) ||
                            cone_meet(c1, cosf(thm), sinf(thm), sa, sb);
                 }
+                pmask |= (pass ? 1u : 0u) << c;
             }
+        }
+        int nlist = 0;
+        for (int tc = tr0; tc < tr1; tc += blockDim.x) {
+            // passing ids of triangles tc .. tc+255 appended in order
+            const int t = tc + threadIdx.x;
+            const bool pass = (pmask >> ((tc - tr0) / 256)) & 1u;
             const unsigned long long bal = __ballot(pass);
             if (lane == 0) s_wc[w] = __popcll(bal);
             __syncthreads();
@@ -311,36 +297,40 @@ __global__ void __launch_bounds__(256) k_cull_1bounce(CullArgs A)
                 }
                 const int incl = wave_incl_scan(mine);
                 const int total = __shfl(incl, kWave - 1, kWave);
-                if (wave_on) {
-                    s_lc[w][lane] = incl - mine;
-#pragma unroll
-                    for (int kw = 0; kw < kCullPts / kWave; ++kw) s_msk[w][lane][kw] = m[kw];
-                }
-                // (block_reserve synchronises the block: the masks are visible after it)
+                const int lc = incl - mine;
+                const int my_tri = tri_ok ? s_list[threadIdx.x] : 0;
                 const unsigned long long base = block_reserve((unsigned long long)total, A.out_count, s_slots);
-                for (int sidx = lane; sidx < total; sidx += kWave) {
-                    // last lane L with s_lc[L] <= sidx, then the pair of that lane's r-th kept bit
-                    int lo = 0, hi = kWave - 1;
-                    while (lo < hi) {
-                        const int mid = (lo + hi + 1) >> 1;
-                        if (s_lc[w][mid] <= sidx) lo = mid;
-                        else hi = mid - 1;
-                    }
-                    int r = sidx - s_lc[w][lo], kw = 0;
-                    unsigned long long mk = s_msk[w][lo][0];
-                    while (r >= __popcll(mk)) {
-                        r -= __popcll(mk);
-                        mk = s_msk[w][lo][++kw];
-                    }
-                    const int k = kw * kWave + select_bit(mk, r);
-                    const unsigned long long idx = base + (unsigned long long)sidx;
-                    if (idx < (unsigned long long)A.cap) {
-                        A.out_x0[idx] = s_j0[k];
-                        A.out_x2[idx] = s_j2[k];
-                        A.out_tri[idx] = s_list[w * kWave + lo];
+                if (total > 0) {
+                    // the wave writes each lane's kept pairs in turn: bit i of
+                    // mask word kw of lane L (pair 64 kw + i) goes to
+                    // base + lc(L) + (kept pairs of L before it), thread i
+                    // handling bit i, so consecutive threads store to
+                    // consecutive slots
+                    for (int L = 0; L < kWave; ++L) {
+                        if (__builtin_amdgcn_readlane(mine, L) == 0) continue;
+                        int pos = __builtin_amdgcn_readlane(lc, L);
+                        const int tL = __builtin_amdgcn_readlane(my_tri, L);
+#pragma unroll
+                        for (int kw = 0; kw < kCullPts / kWave; ++kw) {
+                            const unsigned wlo = __builtin_amdgcn_readlane(unsigned(m[kw]), L);
+                            const unsigned whi = __builtin_amdgcn_readlane(unsigned(m[kw] >> 32), L);
+                            if ((wlo | whi) == 0u) continue;
+                            const int before = __builtin_amdgcn_mbcnt_hi(whi, __builtin_amdgcn_mbcnt_lo(wlo, 0u));
+                            const unsigned mine_bit = lane < 32 ? (wlo >> lane) : (whi >> (lane - 32));
+                            if (mine_bit & 1u) {
+                                const int k = kw * kWave + lane;
+                                const unsigned long long idx = base + (unsigned long long)(pos + before);
+                                if (idx < (unsigned long long)A.cap) {
+                                    A.out_x0[idx] = s_j0[k];
+                                    A.out_x2[idx] = s_j2[k];
+                                    A.out_tri[idx] = tL;
+                                }
+                            }
+                            pos += __popc(wlo) + __popc(whi);
+                        }
                     }
                 }
-                __syncthreads();   // the processed list entries and masks are no longer read
+                __syncthreads();   // the processed list entries are no longer read
                 // move the remaining listed triangles to the front
                 const int rest = nlist - nf;
                 int carry = -1;
