@@ -145,21 +145,57 @@ def _cull_gpu(sp, ctx, mesh, x0, x2, e0, e1, margin=1e-3):
     return q0.cpu().numpy(), q2.cpu().numpy(), qt.cpu().numpy()
 
 
+@pytest.mark.parametrize("sel", ["spread", "tiles", "lights"])
 @pytest.mark.parametrize("ev", ["R", "T"])
-def test_cull_bounds_against_oracle_twin(sp, ctx, ev):
-    _tag(f"cull {ev}")
+def test_cull_bounds_against_oracle_twin(sp, ctx, ev, sel):
+    """GPU-kept triples contain the FP64 twin's (margin 0) and lie inside the
+    widened twin (margin 3e-3).  "spread": 128 points far apart (the tile test
+    of the two-level cull rejects little); "tiles": 8 contiguous 16x16 pixel
+    tiles (it rejects most triangles); "lights": 4 tiles against three lights
+    (tiles of 256 pairs then span 86 points and three lights)."""
+    _tag(f"cull {ev} {sel}")
     mesh = scenes.glints_large_mesh()
-    x0 = scenes.glints_large_points(ev)[::512]
+    P = scenes.glints_large_points(ev)
+    x0 = {"spread": P[::512], "tiles": P[:2048], "lights": P[:1024]}[sel]
     x2 = scenes.GLINTS_LARGE_LIGHT
+    if sel == "lights":
+        x2 = np.array([[0.0, 0.0, 4.0], [0.7, -0.3, 3.0], [-1.5, 0.4, 2.5]])
     e0, e1 = (1.0, 1.0) if ev == "R" else (1.5, 1.0)
     q0, q2, qt = _cull_gpu(sp, ctx, mesh, x0, x2, e0, e1, 1e-3)
-    g = np.zeros((len(x0), 1, mesh.nt), dtype=bool)
+    g = np.zeros((len(x0), len(x2), mesh.nt), dtype=bool)
     g[q0, q2, qt] = True
     assert len(q0) == g.sum()  # no duplicates
     k_tight = oracle.cull_1bounce(mesh.P, mesh.N, mesh.tri, x0, x2, e0, e1, 0.0)
     k_loose = oracle.cull_1bounce(mesh.P, mesh.N, mesh.tri, x0, x2, e0, e1, 3e-3)
     assert np.all(g[k_tight]), "GPU cull dropped a triple the FP64 twin keeps"
     assert np.all(k_loose[g]), "GPU cull kept a triple outside the widened FP64 twin"
+
+
+@pytest.mark.parametrize("ev", ["R", "T"])
+def test_cull_independent_of_point_order(sp, ctx, ev):
+    """The two-level cull keeps the same (point, triangle) set whether the
+    points come in 16x16 pixel tiles or row by row (where a tile of 256 pairs
+    is a whole row and the tile test rejects almost nothing)."""
+    _tag(f"cull point order {ev}")
+    mesh = scenes.glints_large_mesh()
+    z = 2.0 if ev == "R" else -2.0
+    n = 64
+    rows = scenes.points_grid(n, -1.0, 1.0, z)
+    tiled = scenes.points_grid(n, -1.0, 1.0, z, 16)
+    # row-major index of each tiled point
+    ix = np.rint((tiled[:, 0] + 1.0) * n / 2.0 - 0.5).astype(np.int64)
+    iy = np.rint((tiled[:, 1] + 1.0) * n / 2.0 - 0.5).astype(np.int64)
+    perm = iy * n + ix
+    assert np.array_equal(rows[perm], tiled)
+    x2 = scenes.GLINTS_LARGE_LIGHT
+    e0, e1 = (1.0, 1.0) if ev == "R" else (1.5, 1.0)
+    a0, _, at = _cull_gpu(sp, ctx, mesh, rows, x2, e0, e1, 1e-3)
+    b0, _, bt = _cull_gpu(sp, ctx, mesh, tiled, x2, e0, e1, 1e-3)
+    ka = np.sort(a0.astype(np.int64) * mesh.nt + at)
+    kb = np.sort(perm[b0] * mesh.nt + bt)
+    print(ev, "kept", len(ka), len(kb))
+    assert len(ka) > 1000
+    assert np.array_equal(ka, kb)
 
 
 @pytest.mark.parametrize("ev", ["R", "T"])
