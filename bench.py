@@ -32,9 +32,9 @@ PEAK_HBM = 8000.0   # GB/s
 # counters read for a plain 256 MiB device copy (FETCH x2.0, WRITE x1.0).  Valid only for the kernel
 # sources they were taken on (sha256 prefix over the files in _KERNEL_SOURCES, the cull included: it sets
 # the order of the candidates); otherwise traffic is null.
-TRAFFIC_R = {"sha": "cbb63cd0d3fd92cd", "candidates": 99118956,
-             "fetch_kib": 683998.4 + 658976.8 + 34519.1, "write_kib": 1898484.7 + 491008.2 + 41.1,
-             "fetch_scale": 262144.0 / 131084.4, "write_scale": 262144.0 / 262144.0}
+TRAFFIC_R = {"sha": "2e33cac3b84d0211", "candidates": 99118956,
+             "fetch_kib": 680274.5 + 658461.1 + 34517.1, "write_kib": 1897214.1 + 491000.9 + 41.8,
+             "fetch_scale": 262144.0 / 131084.5, "write_scale": 262144.0 / 262144.0}
 _KERNEL_SOURCES = ("onebounce.hip", "spoly_dev.hpp", "laplace_gen.inc", "onebounce.hpp", "cull.hip")
 
 

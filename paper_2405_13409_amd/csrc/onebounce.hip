@@ -876,11 +876,12 @@ __global__ void __launch_bounds__(256) k_ob_coef(OneBounceArgs A)
     }
 }
 
-// Three waves per SIMD is the register target at which the FP64 isolation
-// compiles without scratch (about 160 VGPRs); left to itself the compiler
-// uses all 512 registers of one wave.
+// Register target of the FP64 isolation: left to itself the compiler uses all
+// 512 registers of one wave; at three waves per SIMD it compiles without
+// scratch (about 160 VGPRs), and four waves (128 VGPRs, 104 bytes of spill)
+// measured 0.17 ms faster over the glints refraction list.
 template <typename R, int EV>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_ob_iso(OneBounceArgs A)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_ob_iso(OneBounceArgs A)
 {
     __shared__ unsigned long long s_slots[kMaxBlockWaves + 1];
     constexpr int D1 = Sys<R, EV, 1>::DR, D0 = Sys<R, EV, 0>::DR;
