@@ -56,8 +56,7 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB):
-            build()
+        build()
         L = ctypes.CDLL(LIB)
         P = ctypes.c_void_p
         L.or_solve_1bounce.argtypes = [P, P, P, ctypes.c_int64, P, P, P, P, P, ctypes.c_int64, ctypes.c_int32,
@@ -69,6 +68,7 @@ def lib():
         L.or_resultant_laplace.argtypes = [P, ctypes.c_int32, P, ctypes.c_int32, ctypes.c_int32, P]
         L.or_isolate.argtypes = [P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, P, ctypes.c_int32]
         L.or_det_sign.argtypes = [P, ctypes.c_int32, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double]
+        L.or_res_sign.argtypes = [P, ctypes.c_int32, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double]
         L.or_maxsol.restype = ctypes.c_int
         L.or_cull_tt.argtypes = [P, P, P, ctypes.c_int64, P, ctypes.c_int64, P, ctypes.c_int64, P,
                                  ctypes.c_double, P]
@@ -213,6 +213,16 @@ def det_sign(A: np.ndarray, B: np.ndarray, n: int, v: float) -> int:
     A = _c(A, np.float64)
     B = _c(B, np.float64)
     return int(L.or_det_sign(_p(A), A.shape[0] - 1, _p(B), B.shape[0] - 1, n, v))
+
+
+def res_sign(A: np.ndarray, B: np.ndarray, ma: int, v: float) -> int:
+    """Sign of det R(v) by the product formula (the two-vertex default):
+    product of sgn b(alpha, v) over the real roots alpha of a(., v), whose
+    u-degree is ma."""
+    L = lib()
+    A = _c(A, np.float64)
+    B = _c(B, np.float64)
+    return int(L.or_res_sign(_p(A), A.shape[0] - 1, _p(B), B.shape[0] - 1, int(ma), v))
 
 
 def cull_1bounce(P, N, tri, x0s, x2s, eta0=1.0, eta1=1.0, margin=0.0) -> np.ndarray:

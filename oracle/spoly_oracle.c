@@ -1019,6 +1019,19 @@ int or_det_sign(const double *a_in, int32_t da, const double *b_in, int32_t db, 
     return s;
 }
 
+/* sign of det R(v) through the product formula over the real roots of
+ * a(., v) (u-degree ma), for given bivariate a, b                          */
+int or_res_sign(const double *a_in, int32_t da, const double *b_in, int32_t db, int32_t ma, double v)
+{
+    arena A; A.cap = (size_t)16 << 20; A.top = 0; A.base = (char *)malloc(A.cap);
+    bp a = bp_new(&A, da), b = bp_new(&A, db);
+    memcpy(a.c, a_in, sizeof(double) * (size_t)(da + 1) * (size_t)(da + 1));
+    memcpy(b.c, b_in, sizeof(double) * (size_t)(db + 1) * (size_t)(db + 1));
+    int s = res_sign_product(&A, a, ma, b, 0, v);
+    free(A.base);
+    return s;
+}
+
 int or_maxsol(void) { return OR_MAXSOL; }
 
 /* ================================================================== Normal-cone cull twin (FP64)

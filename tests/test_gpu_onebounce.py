@@ -234,3 +234,72 @@ def test_large_glints_sample_parity_fp32(sp, ctx, ev):
         st = parity.compare_onebounce(sols, orc, diag, len(qt), **tol)
         print(ev, prec, st)
         assert st["compared"] > 50
+
+
+# Two glints reflection candidates (shading-point index into the 256x256 tiled R points, triangle) whose
+# FP32 r(v) lost the oracle's solution: the relabelled e2 system has a near-double root there (a valid
+# and a superfluous root 7e-5 apart), which rounding to FP32 erased.  Found by the full sweep below.
+FP32_TANGENT_CASES = [(320, 18939), (61328, 13757)]
+
+
+def test_fp32_near_tangent_regression(sp, ctx):
+    _tag("fp32 near-tangent regression")
+    mesh = scenes.glints_large_mesh()
+    P = scenes.glints_large_points("R")
+    x2 = scenes.GLINTS_LARGE_LIGHT
+    pi = np.array([c[0] for c in FP32_TANGENT_CASES])
+    qt = np.array([c[1] for c in FP32_TANGENT_CASES], dtype=np.int32)
+    x0 = P[pi]
+    q0 = np.arange(len(pi), dtype=np.int32)
+    q2 = np.zeros(len(pi), dtype=np.int32)
+    keep = oracle.cull_1bounce(mesh.P, mesh.N, mesh.tri, x0, x2, 1.0, 1.0, 0.0)
+    assert keep[q0, 0, qt].all()
+    orc, diag = oracle.solve_1bounce(mesh.P, mesh.N, mesh.tri, x0, x2, q0, q2, qt, "R")
+    assert len(orc) == len(pi)
+    for prec, tol in ((1, parity.FP32), (0, parity.FP64)):
+        sols, _, _ = _run(sp, ctx, mesh, x0, x2, q0, q2, qt, "R", 1.0, 1.0, prec)
+        st = parity.compare_onebounce(sols, orc, diag, len(qt), **tol)
+        assert st["compared"] == len(pi) and st["excluded_instances"] == 0, st
+
+
+@pytest.mark.parametrize("ev", ["R", "T"])
+def test_large_glints_gpu_cull_parity(sp, ctx, ev):
+    """Candidates from the product cull (the GPU's own), as the benchmark solves them."""
+    _tag(f"large glints GPU-cull sample {ev}")
+    mesh = scenes.glints_large_mesh()
+    x0 = scenes.glints_large_points(ev)[1::61]
+    x2 = scenes.GLINTS_LARGE_LIGHT
+    e0, e1 = (1.0, 1.0) if ev == "R" else (1.5, 1.0)
+    q0, q2, qt = _cull_gpu(sp, ctx, mesh, x0, x2, e0, e1, 1e-3)
+    rng = np.random.default_rng(17)
+    s = np.sort(rng.choice(len(q0), min(len(q0), 200000), replace=False))
+    q0, q2, qt = q0[s], q2[s], qt[s]
+    orc, diag = oracle.solve_1bounce(mesh.P, mesh.N, mesh.tri, x0, x2, q0, q2, qt, ev, e0, e1)
+    for prec, tol in ((1, parity.FP32), (0, parity.FP64)):
+        sols, _, _ = _run(sp, ctx, mesh, x0, x2, q0, q2, qt, ev, e0, e1, prec)
+        st = parity.compare_onebounce(sols, orc, diag, len(qt), **tol)
+        print(ev, prec, st)
+        assert st["compared"] > 1000
+
+
+@pytest.mark.parametrize("ev", ["R", "T"])
+def test_large_glints_full_sweep_every_16th_point(sp, ctx, ev):
+    """Every twin-culled candidate of every 16th shading point (6.1M for R,
+    0.8M for T), FP32 and FP64 against the oracle: identical solution sets."""
+    _tag(f"large glints full sweep {ev}")
+    mesh = scenes.glints_large_mesh()
+    x0 = scenes.glints_large_points(ev)[::16]
+    x2 = scenes.GLINTS_LARGE_LIGHT
+    e0, e1 = (1.0, 1.0) if ev == "R" else (1.5, 1.0)
+    q0, q2, qt = np.nonzero(oracle.cull_1bounce(mesh.P, mesh.N, mesh.tri, x0, x2, e0, e1, 0.0))
+    ch = 1 << 21
+    compared = {0: 0, 1: 0}
+    for s in range(0, len(q0), ch):
+        a0, a2, at = q0[s:s + ch], q2[s:s + ch], qt[s:s + ch]
+        orc, diag = oracle.solve_1bounce(mesh.P, mesh.N, mesh.tri, x0, x2, a0, a2, at, ev, e0, e1)
+        for prec, tol in ((1, parity.FP32), (0, parity.FP64)):
+            sols, _, _ = _run(sp, ctx, mesh, x0, x2, a0, a2, at, ev, e0, e1, prec)
+            st = parity.compare_onebounce(sols, orc, diag, len(at), **tol)
+            compared[prec] += st["compared"]
+    print(ev, len(q0), "candidates; compared solutions", compared)
+    assert min(compared.values()) > 10000
