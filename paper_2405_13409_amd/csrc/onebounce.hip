@@ -11,6 +11,13 @@ namespace spoly {
 constexpr int kMaxLaneSol = 4;
 constexpr double kNearDoubleU = 1e-3;   // u-root pairs closer than this are tried from their midpoint
 constexpr double kRefineWindow = 0.005; // FP32 reflection: refine v when the nearest u misses the triangle by less
+// FP32 reflection: a candidate whose r(v) comes within this fraction of sum |r_k|
+// of zero at v = 0, v = 1 or a critical point in [0,1] without the isolation
+// seeing a sign change there (or with one that rounding may have moved) is
+// solved in FP64 instead: a near-double root (the relabelled e2 system has
+// such pairs, one root valid and one superfluous) or a root next to an end of
+// [0,1] can vanish from, or move out of, the FP32 r(v).
+constexpr double kTangentFrac = 1e-3;
 
 struct Geo {            // FP64 geometry of one instance (after the edge relabelling)
     V3<double> p0, e1, e2, n0, dn1, dn2, x0, x2;
@@ -140,10 +147,11 @@ __device__ __forceinline__ R bisect(const R (&c)[D + 1], R lo, R hi, bool neg_lo
 
 template <typename R, int D>
 __device__ __forceinline__ void scan_pieces(const R (&c)[D + 1], const R (&bp)[D], const bool (&bok)[D],
-                                            R (&rt)[D + 1], bool (&ok)[D + 1], R eps)
+                                            R (&rt)[D + 1], bool (&ok)[D + 1], R eps, R* minabs = nullptr)
 {
     R lo = R(0), flo = horner<R, D>(c, R(0));
     R last = R(-1e30);
+    if (minabs) *minabs = fabs(flo);
 #pragma unroll
     for (int k = 0; k <= D; ++k) {
         ok[k] = false;
@@ -152,6 +160,7 @@ __device__ __forceinline__ void scan_pieces(const R (&c)[D + 1], const R (&bp)[D
         R hi = (k < D) ? bp[k] : R(1);
         if (has) {
             R fhi = horner<R, D>(c, hi);
+            if (minabs) *minabs = fmin(*minabs, fabs(fhi));
             if (hi > lo && ((flo < R(0)) != (fhi < R(0)))) {
                 R x = bisect<R, D>(c, lo, hi, flo < R(0), eps);
                 if (x - last > R(1e-12)) {
@@ -166,8 +175,11 @@ __device__ __forceinline__ void scan_pieces(const R (&c)[D + 1], const R (&bp)[D
     }
 }
 
+// With minabs, the smallest |c| over the piece ends (0, 1 and the critical
+// points in between) is returned there.
 template <typename R, int D>
-__device__ __forceinline__ void isolate01(const R (&c)[D + 1], R (&rt)[D + 1], bool (&ok)[D + 1], R eps)
+__device__ __forceinline__ void isolate01(const R (&c)[D + 1], R (&rt)[D + 1], bool (&ok)[D + 1], R eps,
+                                          R* minabs = nullptr)
 {
     R bp[D];
     bool bok[D];
@@ -187,7 +199,7 @@ __device__ __forceinline__ void isolate01(const R (&c)[D + 1], R (&rt)[D + 1], b
             bok[k] = bbok[k];
         }
     }
-    scan_pieces<R, D>(c, bp, bok, rt, ok, eps);
+    scan_pieces<R, D>(c, bp, bok, rt, ok, eps, minabs);
 }
 
 // ---------------------------------------------------------------- path phase (FP64)
@@ -332,12 +344,15 @@ __device__ __forceinline__ bool front_poly_degenerate(const R (&r)[D + 1])
 
 // Coefficients, elimination and isolation: the roots of r(v) in [0,1] in
 // ascending order.  Returns their number (degen set for a degenerate instance).
+// In FP32, `uncertain` is set when r comes within kTangentFrac of zero at a
+// piece end (see kTangentFrac); FP64 never sets it.
 template <typename R, int EV, int F>
 __device__ __forceinline__ int front_roots(const Geo& g, const OneBounceArgs& A, R (&rt)[Sys<R, EV, F>::DR + 1],
-                                           bool (&ok)[Sys<R, EV, F>::DR + 1], int& degen)
+                                           bool (&ok)[Sys<R, EV, F>::DR + 1], int& degen, bool& uncertain)
 {
     using Y = Sys<R, EV, F>;
     R r[Y::DR + 1];
+    uncertain = false;
     if (!front_poly<R, EV, F>(g, A, r)) {
         degen = 1;
 #pragma unroll
@@ -345,7 +360,16 @@ __device__ __forceinline__ int front_roots(const Geo& g, const OneBounceArgs& A,
         return 0;
     }
 
-    isolate01<R, Y::DR>(r, rt, ok, R(A.iso_eps));
+    if constexpr (sizeof(R) == 4) {
+        R minabs;
+        isolate01<R, Y::DR>(r, rt, ok, R(A.iso_eps), &minabs);
+        R l1 = R(0);
+#pragma unroll
+        for (int k = 0; k <= Y::DR; ++k) l1 += fabs(r[k]);
+        uncertain = !(minabs > R(kTangentFrac) * l1);
+    } else {
+        isolate01<R, Y::DR>(r, rt, ok, R(A.iso_eps));
+    }
     int n = 0;
 #pragma unroll
     for (int k = 0; k <= Y::DR; ++k) n += ok[k] ? 1 : 0;
@@ -546,7 +570,16 @@ __device__ __forceinline__ void solve_instance(const Geo& g, const OneBounceArgs
     using Y = Sys<R, EV, F>;
     R rt[Y::DR + 1];
     bool ok[Y::DR + 1];
-    nvr += front_roots<R, EV, F>(g, A, rt, ok, degen);
+    bool uncertain = false;
+    const int n = front_roots<R, EV, F>(g, A, rt, ok, degen, uncertain);
+    if constexpr (sizeof(R) == 4) {
+        if (uncertain) {
+            // rare (a near-tangent or near-end r): the whole candidate in FP64
+            solve_instance<double, EV, F>(g, A, S, nvr, ncand, degen);
+            return;
+        }
+    }
+    nvr += n;
     const P2<double, 1 + F> a64 = a_fp64<F>(g);
 #pragma unroll
     for (int k = 0; k <= Y::DR; ++k)
@@ -697,8 +730,7 @@ __device__ __forceinline__ int front_collect(const Geo& g, const OneBounceArgs& 
     using Y = Sys<R, EV, F>;
     R rt[Y::DR + 1];
     bool ok[Y::DR + 1];
-    const int n = front_roots<R, EV, F>(g, A, rt, ok, degen);
-    uncertain = false;
+    const int n = front_roots<R, EV, F>(g, A, rt, ok, degen, uncertain);
     gather_roots<R, Y::DR>(rt, ok, vr);
     return n;
 }
