@@ -38,8 +38,9 @@ def default_params(two_bounce: bool = False) -> Params:
     """Readings of the constants: tau = 1e-6 on |h^ x n^|; 100 pieces and 10
     bisection steps (Sec. 5.2); u searched on [-m, 1-v+m] before polish with
     m = 1e-4 (one bounce) or 0.05 (two bounces, whose approximate roots can sit
-    up to ~1e-2 away from the exact ones); up to 6 Newton steps."""
-    return Params(1e-6, 0.05 if two_bounce else 1e-4, 1e-8, 6, 100, 10, 1 if two_bounce else 0)
+    up to ~1e-2 away from the exact ones); up to 6 Newton steps; two vertices
+    take the sign of det R(v) from the windowed product formula (det_method 2)."""
+    return Params(1e-6, 0.05 if two_bounce else 1e-4, 1e-8, 6, 100, 10, 2 if two_bounce else 0)
 
 
 def build(force: bool = False) -> str:
@@ -62,6 +63,8 @@ def lib():
         L.or_solve_1bounce.argtypes = [P, P, P, ctypes.c_int64, P, P, P, P, P, ctypes.c_int64, ctypes.c_int32,
                                        ctypes.c_double, ctypes.c_double, P, P, P, P]
         L.or_solve_tt.argtypes = [P, P, P, ctypes.c_int64, P, P, P, P, P, P, ctypes.c_int64, P, P, P, P, P, P]
+        L.or_solve_2v.argtypes = [P, P, P, ctypes.c_int64, P, P, P, P, P, P, ctypes.c_int64, P, P, P, P, P, P, P]
+        L.or_coeffs_2v.argtypes = [P, P, P, ctypes.c_int64, ctypes.c_int64, P, P, P, P, P, P, P, P, P, P, P]
         L.or_coeffs_1bounce.argtypes = [P, P, P, ctypes.c_int64, P, P, ctypes.c_int32, ctypes.c_double,
                                         ctypes.c_double, P, P, P, P, P, P]
         L.or_coeffs_tt.argtypes = [P, P, P, ctypes.c_int64, ctypes.c_int64, P, P, P, P, P, P, P, P, P, P]
@@ -69,6 +72,7 @@ def lib():
         L.or_isolate.argtypes = [P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, P, ctypes.c_int32]
         L.or_det_sign.argtypes = [P, ctypes.c_int32, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double]
         L.or_res_sign.argtypes = [P, ctypes.c_int32, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double]
+        L.or_res_sign_window.argtypes = [P, ctypes.c_int32, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double]
         L.or_maxsol.restype = ctypes.c_int
         L.or_cull_tt.argtypes = [P, P, P, ctypes.c_int64, P, ctypes.c_int64, P, ctypes.c_int64, P,
                                  ctypes.c_double, P]
@@ -133,6 +137,53 @@ def default_sqrt_fit() -> SqrtFit:
     if _fit_cache is None:
         _fit_cache = sqrt_fit_struct()
     return _fit_cache
+
+
+def _chain(chain: str) -> np.ndarray:
+    assert len(chain) == 2 and set(chain) <= {"R", "T"}, chain
+    return np.array([0 if c == "R" else 1 for c in chain], dtype=np.int32)
+
+
+def solve_2v(P, N, tri, x0s, x3s, q_x0, q_x3, q_t1, q_t2, chain: str, eta=(1.0, 1.5, 1.0),
+             params: Params | None = None, fit: SqrtFit | None = None):
+    """Two specular vertices; chain "RR", "RT", "TR" or "TT" (event at x1, then at x2)."""
+    L = lib()
+    P, N, x0s, x3s = (_c(a, np.float64) for a in (P, N, x0s, x3s))
+    tri, q_x0, q_x3, q_t1, q_t2 = (_c(a, np.int32) for a in (tri, q_x0, q_x3, q_t1, q_t2))
+    nq = len(q_t1)
+    ms = maxsol()
+    out = np.zeros(nq * ms, dtype=SOL_DTYPE)
+    cnt = np.zeros(nq, dtype=np.int32)
+    diag = np.zeros(nq, dtype=DIAG_DTYPE)
+    eta = _c(eta, np.float64)
+    ch = _chain(chain)
+    prm = params or default_params(True)
+    fit = fit or default_sqrt_fit()
+    L.or_solve_2v(_p(P), _p(N), _p(tri), len(tri), _p(x0s), _p(x3s), _p(q_x0), _p(q_x3), _p(q_t1), _p(q_t2), nq,
+                  _p(eta), _p(ch), ctypes.byref(fit), ctypes.byref(prm), _p(out), _p(cnt), _p(diag))
+    sel = (np.arange(ms)[None, :] < cnt[:, None]).ravel()
+    sols = out[sel]
+    sols = sols[np.lexsort((sols["u1"], sols["v1"], sols["query"]))]
+    return sols, diag
+
+
+def coeffs_2v(P, N, tri, t1: int, t2: int, x0, x3, chain: str, eta=(1.0, 1.5, 1.0), fit: SqrtFit | None = None):
+    L = lib()
+    P, N = _c(P, np.float64), _c(N, np.float64)
+    tri = _c(tri, np.int32)
+    x0 = _c(x0, np.float64).reshape(3)
+    x3 = _c(x3, np.float64).reshape(3)
+    eta = _c(eta, np.float64)
+    ch = _chain(chain)
+    fit = fit or default_sqrt_fit()
+    a = np.zeros(49 * 49)
+    b = np.zeros(49 * 49)
+    da, db, nb, fl = (ctypes.c_int32() for _ in range(4))
+    L.or_coeffs_2v(_p(P), _p(N), _p(tri), int(t1), int(t2), _p(x0), _p(x3), _p(eta), _p(ch), ctypes.byref(fit),
+                   _p(a), ctypes.byref(da), _p(b), ctypes.byref(db), ctypes.byref(nb), ctypes.byref(fl))
+    A = a[:(da.value + 1) ** 2].reshape(da.value + 1, da.value + 1)
+    B = b[:(db.value + 1) ** 2].reshape(db.value + 1, db.value + 1)
+    return A, B, nb.value, fl.value
 
 
 def solve_tt(P, N, tri, x0s, x3s, q_x0, q_x3, q_t1, q_t2, eta=(1.0, 1.5, 1.0), params: Params | None = None,
@@ -216,13 +267,21 @@ def det_sign(A: np.ndarray, B: np.ndarray, n: int, v: float) -> int:
 
 
 def res_sign(A: np.ndarray, B: np.ndarray, ma: int, v: float) -> int:
-    """Sign of det R(v) by the product formula (the two-vertex default):
-    product of sgn b(alpha, v) over the real roots alpha of a(., v), whose
-    u-degree is ma."""
+    """Sign of det R(v) by the product formula (det_method 1): product of
+    sgn b(alpha, v) over all real roots alpha of a(., v), whose u-degree is ma."""
     L = lib()
     A = _c(A, np.float64)
     B = _c(B, np.float64)
     return int(L.or_res_sign(_p(A), A.shape[0] - 1, _p(B), B.shape[0] - 1, int(ma), v))
+
+
+def res_sign_window(A: np.ndarray, B: np.ndarray, ma: int, v: float) -> int:
+    """The two-vertex default (det_method 2): the product of sgn b(alpha, v)
+    over the real roots alpha of a(., v) with u in [-1, 2]."""
+    L = lib()
+    A = _c(A, np.float64)
+    B = _c(B, np.float64)
+    return int(L.or_res_sign_window(_p(A), A.shape[0] - 1, _p(B), B.shape[0] - 1, int(ma), v))
 
 
 def cull_1bounce(P, N, tri, x0s, x2s, eta0=1.0, eta1=1.0, margin=0.0) -> np.ndarray:

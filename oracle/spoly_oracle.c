@@ -50,7 +50,9 @@ typedef struct {
     int32_t pieces;      /* uniform pieces of [0,1] for the >=2-bounce scan (100)       */
     int32_t bisect_iters;/* bisection steps per sign change (10)                        */
     int32_t det_method;  /* sign of det R(v): 0 Gaussian elimination on the Bezout matrix, */
-                         /* 1 product formula over the real roots of a(.,v)              */
+                         /* 1 product formula over the real roots of a(.,v),             */
+                         /* 2 the same product over the real roots in the window         */
+                         /*   u in [-1, 2] (the two-vertex default)                      */
 } or_params;
 
 typedef struct {
@@ -657,12 +659,17 @@ int or_isolate(const double *c, int32_t d, double lo, double hi, double *roots, 
     return n;
 }
 
-/* ================================================================== two bounces (TT)
- * Chain x0 -> x1 on T1 -> x2 on T2 -> x3, refraction at both vertices, IORs
- * eta[0] (segment x0x1), eta[1] (x1x2), eta[2] (x2x3).
+/* ================================================================== two bounces (RR, RT, TR, TT)
+ * Chain x0 -> x1 on T1 -> x2 on T2 -> x3, reflection (R) or refraction (T) at
+ * each vertex, IORs eta[0] (segment x0x1), eta[1] (x1x2), eta[2] (x2x3); a
+ * reflection has equal IORs on both of its segments.
  *
- * Coefficient phase:
- *   d0 = x1 - x0, n1 = N1 u;  beta = n1^2 d0^2 - eta'^2 (n1^2 d0^2 - (d0.n1)^2),
+ * Coefficient phase (Sec. 4.4-4.5):
+ *   d0 = x1 - x0, n1 = N1 u.
+ *   Direction x1 -> x2 (Eq. eq_431_di):
+ *   R at x1: Dt = |n1|^2 d0 - 2 (d0.n1) n1, the reflected direction scaled by
+ *     |n1|^2 (exact, polynomial);
+ *   T at x1: beta = n1^2 d0^2 - eta'^2 (n1^2 d0^2 - (d0.n1)^2),
  *   eta' = eta0/eta1                                             (Eq. eq_refr_rational)
  *   sqrt(beta) ~ sqrt(S) R_p(beta/S), R_p(s) = (c0 + c1 s)/(d0 + d1 s)   (Sec. 4.4)
  *     reading: S = n1^2 d0^2 at the centroid of T1 (a per-tuple constant) and the
@@ -676,37 +683,52 @@ int or_isolate(const double *c, int32_t d, double lo, double hi, double *roots, 
  *   D2 = kappa x3 - X2 (= kappa d2).
  *   Since d1 = x2 - x1 is parallel to Dt, Dt replaces d1 in both constraints at x2:
  *   a = (Dt x (x3 - x1)) . M2                                         (Eq. eq_coplane)
- *   b = eta1^2 |D2|^2 ((Dt x M2).b)^2 - eta2^2 |Dt|^2 ((D2 x M2).b)^2  (Eq. eq_cpf_result)
- *   Structural degrees with D = 3 + 4 f1 (f = 1 for interpolated normals):
- *   deg a = 2D + 1 + f2, deg b = 6D + 2 + 2 f2, u-degree = total degree.
+ *   T at x2: b = eta1^2 |D2|^2 ((Dt x M2).b)^2 - eta2^2 |Dt|^2 ((D2 x M2).b)^2
+ *                                                                      (Eq. eq_cpf_result)
+ *   R at x2: b = (Dt.M2)(D2.t) + (Dt.t)(D2.M2), t = M2 x e              (Eq. eq_pf_result)
+ *            with e = e21 of T2, or e22 by the product-form rule at x2.
+ *   Structural degrees with f = 1 for interpolated normals, D = deg Dt
+ *   (R: 1 + 2 f1; T: 3 + 4 f1): deg a = 2D + 1 + f2; deg b = 6D + 2 + 2 f2 (T at
+ *   x2) or 4D + 1 + 2 f2 (R at x2); u-degree = total degree.
  */
 typedef struct { double bp[7]; double c[6][4]; } or_sqrtfit;  /* breakpoints, (c0,c1,d0,d1) per piece */
 
-static int coeffs_tt(arena *A, const tri_t *T1, const tri_t *T2, v3 x0, v3 x3, const double *eta,
-                     const or_sqrtfit *fit, bp *pa, bp *pb, int *flags)
+static int coeffs_2v(arena *A, const tri_t *T1, const tri_t *T2, v3 x0, v3 x3, const double *eta,
+                     int ev1, int ev2, const or_sqrtfit *fit, bp *pa, bp *pb, int *flags)
 {
     int f1 = T1->flat ? 0 : 1, f2 = T2->flat ? 0 : 1;
-    double etap = eta[0] / eta[1];
     bv x1 = tri_xpoly(A, T1);
     bv n1 = tri_npoly(A, T1);
     bv d0 = bv_sub(A, x1, bv_const(A, x0));
-    bp nn = bv_dot(A, n1, n1), dd = bv_dot(A, d0, d0), dn = bv_dot(A, d0, n1);
-    bp nndd = bp_mul(A, nn, dd);
-    bp beta = bp_lc(A, 1.0 - etap * etap, nndd, etap * etap, bp_mul(A, dn, dn));
-    /* per-tuple constants at the centroid of T1 */
-    v3 c1 = tri_x(T1, 1.0 / 3.0, 1.0 / 3.0), nc1 = tri_n(T1, 1.0 / 3.0, 1.0 / 3.0);
-    v3 d0c = vsub(c1, x0);
-    double S = vdot(nc1, nc1) * vdot(d0c, d0c);
-    double dnc = vdot(d0c, nc1);
-    double sc = 1.0 - etap * etap * (1.0 - dnc * dnc / S);   /* beta/S at the centroid */
-    int p = 0;
-    for (int k = 1; k < 6; ++k) if (sc >= fit->bp[k]) p = k;
-    double q0 = fit->c[p][0], q1 = fit->c[p][1], r0 = fit->c[p][2], r1 = fit->c[p][3];
-    bp num = bp_lc(A, q1 / S, beta, q0, bp_const(A, 1.0));
-    bp den = bp_lc(A, r1 / S, beta, r0, bp_const(A, 1.0));
-    double sg = dnc < 0.0 ? -1.0 : 1.0;
-    bv tang = bv_sub(A, bv_smul(A, nn, d0), bv_smul(A, dn, n1));          /* d0 n^2 - (d0.n) n */
-    bv Dt = bv_add(A, bv_kmul(A, etap, bv_smul(A, den, tang)), bv_kmul(A, sg * sqrt(S), bv_smul(A, num, n1)));
+    bp nn = bv_dot(A, n1, n1), dn = bv_dot(A, d0, n1);
+    v3 c1 = tri_x(T1, 1.0 / 3.0, 1.0 / 3.0);
+    bv Dt;
+    int D;
+    if (ev1 == 0) {
+        /* reflection: |n1|^2 d0 - 2 (d0.n1) n1 */
+        Dt = bv_sub(A, bv_smul(A, nn, d0), bv_kmul(A, 2.0, bv_smul(A, dn, n1)));
+        D = 1 + 2 * f1;
+    } else {
+        double etap = eta[0] / eta[1];
+        bp dd = bv_dot(A, d0, d0);
+        bp nndd = bp_mul(A, nn, dd);
+        bp beta = bp_lc(A, 1.0 - etap * etap, nndd, etap * etap, bp_mul(A, dn, dn));
+        /* per-tuple constants at the centroid of T1 */
+        v3 nc1 = tri_n(T1, 1.0 / 3.0, 1.0 / 3.0);
+        v3 d0c = vsub(c1, x0);
+        double S = vdot(nc1, nc1) * vdot(d0c, d0c);
+        double dnc = vdot(d0c, nc1);
+        double sc = 1.0 - etap * etap * (1.0 - dnc * dnc / S);   /* beta/S at the centroid */
+        int p = 0;
+        for (int k = 1; k < 6; ++k) if (sc >= fit->bp[k]) p = k;
+        double q0 = fit->c[p][0], q1 = fit->c[p][1], r0 = fit->c[p][2], r1 = fit->c[p][3];
+        bp num = bp_lc(A, q1 / S, beta, q0, bp_const(A, 1.0));
+        bp den = bp_lc(A, r1 / S, beta, r0, bp_const(A, 1.0));
+        double sg = dnc < 0.0 ? -1.0 : 1.0;
+        bv tang = bv_sub(A, bv_smul(A, nn, d0), bv_smul(A, dn, n1));          /* d0 n^2 - (d0.n) n */
+        Dt = bv_add(A, bv_kmul(A, etap, bv_smul(A, den, tang)), bv_kmul(A, sg * sqrt(S), bv_smul(A, num, n1)));
+        D = 3 + 4 * f1;
+    }
     /* rational coordinate mapping onto T2 */
     bv q = bv_sub(A, x1, bv_const(A, T2->p0));
     bv Dxe22 = bv_cross(A, Dt, bv_const(A, T2->e2));
@@ -719,6 +741,14 @@ static int coeffs_tt(arena *A, const tri_t *T1, const tri_t *T2, v3 x0, v3 x3, c
     bv D2 = bv_sub(A, bv_vmul(A, ka, x3), X2);
     *pa = bv_dot(A, bv_cross(A, Dt, bv_sub(A, bv_const(A, x3), x1)), M2);
     v3 c2 = tri_x(T2, 1.0 / 3.0, 1.0 / 3.0);
+    if (ev2 == 0) {
+        int use2 = pick_edge2(c2, c1, x3, T2->e1, T2->e2);
+        if (use2) *flags |= OR_F_EDGE2;
+        bv t = bv_cross(A, M2, bv_const(A, use2 ? T2->e2 : T2->e1));
+        *pb = bp_add(A, bp_mul(A, bv_dot(A, Dt, M2), bv_dot(A, D2, t)),
+                        bp_mul(A, bv_dot(A, Dt, t), bv_dot(A, D2, M2)));
+        return 4 * D + 1 + 2 * f2;  /* structural u-degree of b */
+    }
     v3 ax;
     *flags |= pick_axis(c2, c1, x3, &ax);
     bp l = bv_dotc(A, bv_cross(A, Dt, M2), ax);
@@ -726,9 +756,7 @@ static int coeffs_tt(arena *A, const tri_t *T1, const tri_t *T2, v3 x0, v3 x3, c
     bp t1 = bp_mul(A, bv_dot(A, D2, D2), bp_mul(A, l, l));
     bp t2 = bp_mul(A, bv_dot(A, Dt, Dt), bp_mul(A, r, r));
     *pb = bp_lc(A, eta[1] * eta[1], t1, -eta[2] * eta[2], t2);
-    int D = 3 + 4 * f1;
-    (void)D;
-    return 6 * (3 + 4 * f1) + 2 + 2 * f2;  /* structural u-degree of b = Bezout size */
+    return 6 * D + 2 + 2 * f2;  /* structural u-degree of b */
 }
 
 /* sign of det of the numeric Bezout matrix at v, by Gaussian elimination with
@@ -774,20 +802,26 @@ static int det_sign_at(arena *A, bp a, bp b, int n, double v)
     return sign;
 }
 
-/* exact refraction at x1 and intersection with T2's plane.  Returns 0 on total
- * internal reflection or when the plane is behind / parallel.               */
-static int trace_x2(const tri_t *T1, const tri_t *T2, v3 x0, double u1, double v1, double etap,
+/* exact reflection (ev1 = 0) or refraction (ev1 = 1) at x1 and intersection
+ * with T2's plane.  Returns 0 on total internal reflection or when the plane
+ * is behind / parallel.                                                     */
+static int trace_x2(const tri_t *T1, const tri_t *T2, v3 x0, double u1, double v1, int ev1, double etap,
                     double *u2, double *v2, v3 *x1o, v3 *x2o)
 {
     v3 x1 = tri_x(T1, u1, v1);
     v3 n = vnorm(tri_n(T1, u1, v1));
     v3 di = vnorm(vsub(x1, x0));
     double c = vdot(di, n);
-    if (c > 0) { n = vmul(n, -1.0); c = -c; }          /* orient n against the incoming ray */
-    double ci = -c;
-    double k = 1.0 - etap * etap * (1.0 - ci * ci);
-    if (k < 0.0) return 0;
-    v3 dt = vadd(vmul(di, etap), vmul(n, etap * ci - sqrt(k)));
+    v3 dt;
+    if (ev1 == 0) {
+        dt = vsub(di, vmul(n, 2.0 * c));
+    } else {
+        if (c > 0) { n = vmul(n, -1.0); c = -c; }          /* orient n against the incoming ray */
+        double ci = -c;
+        double k = 1.0 - etap * etap * (1.0 - ci * ci);
+        if (k < 0.0) return 0;
+        dt = vadd(vmul(di, etap), vmul(n, etap * ci - sqrt(k)));
+    }
     /* Moller-Trumbore without bounds */
     v3 pv = vcross(dt, T2->e2);
     double det = vdot(T2->e1, pv);
@@ -803,11 +837,11 @@ static int trace_x2(const tri_t *T1, const tri_t *T2, v3 x0, double u1, double v
 }
 
 /* F(u1,v1): (h2^ x n2^) on a fixed tangent basis of T2, x2 from the exact ray */
-static int tt_residual(const tri_t *T1, const tri_t *T2, v3 x0, v3 x3, const double *eta,
+static int tt_residual(const tri_t *T1, const tri_t *T2, v3 x0, v3 x3, const double *eta, int ev1,
                        v3 ta, v3 tb, double u1, double v1, double F[2])
 {
     double u2, v2; v3 x1, x2;
-    if (!trace_x2(T1, T2, x0, u1, v1, eta[0] / eta[1], &u2, &v2, &x1, &x2)) return 0;
+    if (!trace_x2(T1, T2, x0, u1, v1, ev1, eta[0] / eta[1], &u2, &v2, &x1, &x2)) return 0;
     v3 n2 = vnorm(tri_n(T2, u2, v2));
     v3 wi = vnorm(vsub(x1, x2)), wo = vnorm(vsub(x3, x2));
     v3 h = vnorm(vadd(vmul(wi, eta[1]), vmul(wo, eta[2])));
@@ -818,7 +852,7 @@ static int tt_residual(const tri_t *T1, const tri_t *T2, v3 x0, v3 x3, const dou
 
 /* Newton polish with a central-difference Jacobian (reading of the one
  * Newton iteration of Sec. 7, applied to the exact constraints).            */
-static int polish_tt(const tri_t *T1, const tri_t *T2, v3 x0, v3 x3, const double *eta, int iters,
+static int polish_tt(const tri_t *T1, const tri_t *T2, v3 x0, v3 x3, const double *eta, int ev1, int iters,
                      double *pu, double *pv)
 {
     v3 nc = vnorm(tri_n(T2, 1.0 / 3.0, 1.0 / 3.0));
@@ -828,11 +862,11 @@ static int polish_tt(const tri_t *T1, const tri_t *T2, v3 x0, v3 x3, const doubl
     const double h = 1e-6;
     for (int it = 0; it < iters; ++it) {
         double F[2], Fu1[2], Fu0[2], Fv1[2], Fv0[2];
-        if (!tt_residual(T1, T2, x0, x3, eta, ta, tb, u, v, F)) return 0;
-        if (!tt_residual(T1, T2, x0, x3, eta, ta, tb, u + h, v, Fu1)) return 0;
-        if (!tt_residual(T1, T2, x0, x3, eta, ta, tb, u - h, v, Fu0)) return 0;
-        if (!tt_residual(T1, T2, x0, x3, eta, ta, tb, u, v + h, Fv1)) return 0;
-        if (!tt_residual(T1, T2, x0, x3, eta, ta, tb, u, v - h, Fv0)) return 0;
+        if (!tt_residual(T1, T2, x0, x3, eta, ev1, ta, tb, u, v, F)) return 0;
+        if (!tt_residual(T1, T2, x0, x3, eta, ev1, ta, tb, u + h, v, Fu1)) return 0;
+        if (!tt_residual(T1, T2, x0, x3, eta, ev1, ta, tb, u - h, v, Fu0)) return 0;
+        if (!tt_residual(T1, T2, x0, x3, eta, ev1, ta, tb, u, v + h, Fv1)) return 0;
+        if (!tt_residual(T1, T2, x0, x3, eta, ev1, ta, tb, u, v - h, Fv0)) return 0;
         double J00 = (Fu1[0] - Fu0[0]) / (2 * h), J10 = (Fu1[1] - Fu0[1]) / (2 * h);
         double J01 = (Fv1[0] - Fv0[0]) / (2 * h), J11 = (Fv1[1] - Fv0[1]) / (2 * h);
         double det = J00 * J11 - J01 * J10;
@@ -872,8 +906,12 @@ static int res_sign_product(arena *A, bp a, int ma, bp b, int n, double v)
         for (int j = b.d - i; j >= 0; --j) s = s * v + b.c[i * (b.d + 1) + j];
         bi[i] = s;
     }
-    /* the structural u-degree of b is even for the TT system (6D + 2 + 2 f2), so
-     * sgn(lc(a))^(deg b) = +1 */
+    /* The factor sgn(lc(a))^(deg b) is left out: it is +1 when deg_u b is even
+     * (a refraction at x2: 6D + 2 + 2 f2) and a constant sign when lc_u(a) is a
+     * constant (no top row of a dropped).  Otherwise (deg b odd: a reflection
+     * at x2) each zero of lc_u(a)(v) in [0,1] adds a sign change that is not a
+     * root of the resultant; its v yields no admissible path and the path phase
+     * rejects it. */
     int sign = 1;
     (void)n;
     if (ai[ma] == 0.0) { A->top = mark; return 1; }
@@ -895,8 +933,47 @@ static int res_sign_product(arena *A, bp a, int ma, bp b, int n, double v)
     return sign;
 }
 
-static void solve_tt(arena *A, const tri_t *T1, const tri_t *T2, v3 x0, v3 x3, const double *eta,
-                     const or_sqrtfit *fit, const or_params *prm, int32_t qid,
+/* Windowed product sign: the product of sgn b(alpha, v) over the real roots
+ * alpha of a(., v) with u in [-1, 2], the triangle and one triangle width
+ * around it.  Reading (two vertices): the full product of res_sign_product
+ * also multiplies in roots of a far outside T1 (where the direction x1 -> x2
+ * turns parallel to T2's plane, x2 goes to infinity and a and b nearly share a
+ * root), and there the FP64 value of b is rounding noise whose sign flips from
+ * one v to the next.  A root of the window contributes the same factor to both
+ * functions, so every sign change of the full product that comes from a root
+ * of the resultant with u in the window, every physical solution among them,
+ * is a sign change of this one too.  The windowed product also changes sign
+ * where a root crosses u = -1 or u = 2 with b < 0 there; the v it yields has
+ * no admissible u and the path phase rejects it.                             */
+static int res_sign_window(arena *A, bp a, int ma, bp b, double v)
+{
+    size_t mark = A->top;
+    double *ai = (double *)ar_alloc(A, sizeof(double) * (size_t)(ma + 1));
+    double *bi = (double *)ar_alloc(A, sizeof(double) * (size_t)(b.d + 1));
+    for (int i = 0; i <= ma; ++i) {
+        double s = 0.0;
+        for (int j = a.d - i; j >= 0; --j) s = s * v + a.c[i * (a.d + 1) + j];
+        ai[i] = s;
+    }
+    for (int i = 0; i <= b.d; ++i) {
+        double s = 0.0;
+        for (int j = b.d - i; j >= 0; --j) s = s * v + b.c[i * (b.d + 1) + j];
+        bi[i] = s;
+    }
+    int sign = 1;
+    double roots[64];
+    int nr = isolate(A, ai, ma, -1.0, 2.0, roots, 64);
+    for (int k = 0; k < nr; ++k) {
+        double s = 0.0;
+        for (int i = b.d; i >= 0; --i) s = s * roots[k] + bi[i];
+        if (s < 0.0) sign = -sign;
+    }
+    A->top = mark;
+    return sign;
+}
+
+static void solve_2v(arena *A, const tri_t *T1, const tri_t *T2, v3 x0, v3 x3, const double *eta,
+                     int ev1, int ev2, const or_sqrtfit *fit, const or_params *prm, int32_t qid,
                      or_sol *out, int32_t *nout, or_diag *dg)
 {
     memset(dg, 0, sizeof(*dg));
@@ -904,7 +981,7 @@ static void solve_tt(arena *A, const tri_t *T1, const tri_t *T2, v3 x0, v3 x3, c
     if (T1->flat) dg->flags |= OR_F_FLAT1;
     if (T2->flat) dg->flags |= OR_F_FLAT2;
     bp a, b;
-    int nb = coeffs_tt(A, T1, T2, x0, x3, eta, fit, &a, &b, &dg->flags);
+    int nb = coeffs_2v(A, T1, T2, x0, x3, eta, ev1, ev2, fit, &a, &b, &dg->flags);
     int ma = numeric_udeg(a, a.d);
     nb = numeric_udeg(b, nb);
     int n = ma > nb ? ma : nb;
@@ -912,7 +989,8 @@ static void solve_tt(arena *A, const tri_t *T1, const tri_t *T2, v3 x0, v3 x3, c
     /* piecewise sign scan of det R(v) on [0,1] */
     int P = prm->pieces;
     int *sg = (int *)ar_alloc(A, sizeof(int) * (size_t)(P + 1));
-#define DETSIGN(vv) (prm->det_method == 1 ? res_sign_product(A, a, ma, b, n, (vv)) : det_sign_at(A, a, b, n, (vv)))
+#define DETSIGN(vv) (prm->det_method == 2 ? res_sign_window(A, a, ma, b, (vv)) : \
+                     prm->det_method == 1 ? res_sign_product(A, a, ma, b, n, (vv)) : det_sign_at(A, a, b, n, (vv)))
     for (int j = 0; j <= P; ++j) sg[j] = DETSIGN((double)j / P);
     double vr[OR_MAXSOL * 8];
     int nv = 0;
@@ -943,14 +1021,14 @@ static void solve_tt(arena *A, const tri_t *T1, const tri_t *T2, v3 x0, v3 x3, c
         for (int m = 0; m < nu; ++m) {
             double u = ur[m], vv = v;
             dg->n_cand++;
-            if (!polish_tt(T1, T2, x0, x3, eta, prm->polish_iters, &u, &vv)) continue;
+            if (!polish_tt(T1, T2, x0, x3, eta, ev1, prm->polish_iters, &u, &vv)) continue;
             if (!bary_inside(u, vv)) continue;
             double u2, v2; v3 x1, x2;
-            if (!trace_x2(T1, T2, x0, u, vv, etap, &u2, &v2, &x1, &x2)) continue;
+            if (!trace_x2(T1, T2, x0, u, vv, ev1, etap, &u2, &v2, &x1, &x2)) continue;
             if (!bary_inside(u2, v2)) continue;
             double r1, r2;
-            if (!vertex_law(x0, x1, x2, tri_n(T1, u, vv), eta[0], eta[1], 1, &r1)) continue;
-            if (!vertex_law(x1, x2, x3, tri_n(T2, u2, v2), eta[1], eta[2], 1, &r2)) continue;
+            if (!vertex_law(x0, x1, x2, tri_n(T1, u, vv), eta[0], eta[1], ev1, &r1)) continue;
+            if (!vertex_law(x1, x2, x3, tri_n(T2, u2, v2), eta[1], eta[2], ev2, &r2)) continue;
             double res = fmax(r1, r2);
             if (!(res <= prm->tau)) continue;
             or_sol s;
@@ -964,10 +1042,11 @@ static void solve_tt(arena *A, const tri_t *T1, const tri_t *T2, v3 x0, v3 x3, c
     *nout = nsol;
 }
 
-int or_solve_tt(const double *P, const double *N, const int32_t *tri, int64_t nt,
+/* chain[0], chain[1]: event at x1 and at x2 (0 = reflection, 1 = refraction) */
+int or_solve_2v(const double *P, const double *N, const int32_t *tri, int64_t nt,
                 const double *x0s, const double *x3s,
                 const int32_t *q_x0, const int32_t *q_x3, const int32_t *q_t1, const int32_t *q_t2, int64_t nq,
-                const double *eta, const or_sqrtfit *fit, const or_params *prm,
+                const double *eta, const int32_t *chain, const or_sqrtfit *fit, const or_params *prm,
                 or_sol *out, int32_t *count, or_diag *diag)
 {
     (void)nt;
@@ -980,23 +1059,33 @@ int or_solve_tt(const double *P, const double *N, const int32_t *tri, int64_t nt
             A.top = 0;
             tri_t T1 = load_tri(P, N, tri, q_t1[q]);
             tri_t T2 = load_tri(P, N, tri, q_t2[q]);
-            solve_tt(&A, &T1, &T2, vload(x0s, q_x0[q]), vload(x3s, q_x3[q]), eta, fit, prm, (int32_t)q,
-                     out + q * OR_MAXSOL, count + q, diag + q);
+            solve_2v(&A, &T1, &T2, vload(x0s, q_x0[q]), vload(x3s, q_x3[q]), eta, chain[0], chain[1], fit, prm,
+                     (int32_t)q, out + q * OR_MAXSOL, count + q, diag + q);
         }
         free(A.base);
     }
     return 0;
 }
 
-/* TT coefficients for the pin tests (dense (d+1)^2 arrays, capacity 47*47) */
-int or_coeffs_tt(const double *P, const double *N, const int32_t *tri, int64_t t1, int64_t t2,
-                 const double *x0, const double *x3, const double *eta, const or_sqrtfit *fit,
+int or_solve_tt(const double *P, const double *N, const int32_t *tri, int64_t nt,
+                const double *x0s, const double *x3s,
+                const int32_t *q_x0, const int32_t *q_x3, const int32_t *q_t1, const int32_t *q_t2, int64_t nq,
+                const double *eta, const or_sqrtfit *fit, const or_params *prm,
+                or_sol *out, int32_t *count, or_diag *diag)
+{
+    const int32_t tt[2] = {1, 1};
+    return or_solve_2v(P, N, tri, nt, x0s, x3s, q_x0, q_x3, q_t1, q_t2, nq, eta, tt, fit, prm, out, count, diag);
+}
+
+/* two-vertex coefficients for the pin tests (dense (d+1)^2 arrays, capacity 49*49) */
+int or_coeffs_2v(const double *P, const double *N, const int32_t *tri, int64_t t1, int64_t t2,
+                 const double *x0, const double *x3, const double *eta, const int32_t *chain, const or_sqrtfit *fit,
                  double *a_out, int32_t *da, double *b_out, int32_t *db, int32_t *n_bez, int32_t *flags)
 {
     arena A; A.cap = (size_t)64 << 20; A.top = 0; A.base = (char *)malloc(A.cap);
     tri_t T1 = load_tri(P, N, tri, t1), T2 = load_tri(P, N, tri, t2);
     bp a, b; int fl = 0;
-    int nb = coeffs_tt(&A, &T1, &T2, vload(x0, 0), vload(x3, 0), eta, fit, &a, &b, &fl);
+    int nb = coeffs_2v(&A, &T1, &T2, vload(x0, 0), vload(x3, 0), eta, chain[0], chain[1], fit, &a, &b, &fl);
     int ma = numeric_udeg(a, a.d);
     nb = numeric_udeg(b, nb);
     int n = ma > nb ? ma : nb;
@@ -1005,6 +1094,14 @@ int or_coeffs_tt(const double *P, const double *N, const int32_t *tri, int64_t t
     memcpy(b_out, b.c, sizeof(double) * (size_t)(b.d + 1) * (size_t)(b.d + 1));
     free(A.base);
     return 0;
+}
+
+int or_coeffs_tt(const double *P, const double *N, const int32_t *tri, int64_t t1, int64_t t2,
+                 const double *x0, const double *x3, const double *eta, const or_sqrtfit *fit,
+                 double *a_out, int32_t *da, double *b_out, int32_t *db, int32_t *n_bez, int32_t *flags)
+{
+    const int32_t tt[2] = {1, 1};
+    return or_coeffs_2v(P, N, tri, t1, t2, x0, x3, eta, tt, fit, a_out, da, b_out, db, n_bez, flags);
 }
 
 /* sign of det R(v) for given bivariate a, b and Bezout size n */
@@ -1028,6 +1125,18 @@ int or_res_sign(const double *a_in, int32_t da, const double *b_in, int32_t db, 
     memcpy(a.c, a_in, sizeof(double) * (size_t)(da + 1) * (size_t)(da + 1));
     memcpy(b.c, b_in, sizeof(double) * (size_t)(db + 1) * (size_t)(db + 1));
     int s = res_sign_product(&A, a, ma, b, 0, v);
+    free(A.base);
+    return s;
+}
+
+/* windowed product sign (det_method 2) for given bivariate a, b */
+int or_res_sign_window(const double *a_in, int32_t da, const double *b_in, int32_t db, int32_t ma, double v)
+{
+    arena A; A.cap = (size_t)16 << 20; A.top = 0; A.base = (char *)malloc(A.cap);
+    bp a = bp_new(&A, da), b = bp_new(&A, db);
+    memcpy(a.c, a_in, sizeof(double) * (size_t)(da + 1) * (size_t)(da + 1));
+    memcpy(b.c, b_in, sizeof(double) * (size_t)(db + 1) * (size_t)(db + 1));
+    int s = res_sign_window(&A, a, ma, b, v);
     free(A.base);
     return s;
 }

@@ -22,6 +22,11 @@ its glint and caustic workloads of Sec. 6):
 * ``icosphere(levels, radius)`` -- icosahedron subdivided ``levels`` times with
   midpoints projected to the sphere; smooth normals = position / radius.
   Faces are oriented outward.
+* ``mirror_gap(N, gap, ...)`` -- two wavy heightfields facing each other across
+  a gap (stand-in for the paper's two-reflection glints scene): the bottom one
+  z = h_b(x, y) with normals up (triangles 0 .. nt/2 - 1), the top one
+  z = gap - h_t(x, y) with normals down (triangles nt/2 .. nt - 1), both built
+  as ``heightfield`` with their own seeds.
 """
 from __future__ import annotations
 
@@ -123,6 +128,19 @@ def icosphere(levels: int = 3, radius: float = 0.5, center=(0.0, 0.0, 0.0)) -> M
     return Mesh(P, U.copy(), tri)
 
 
+def mirror_gap(N: int = 16, gap: float = 1.0, A: float = 0.05, J: int = 3, f_lo: float = 1.0, f_hi: float = 4.0,
+               seed_bottom: int = 6, seed_top: int = 7) -> Mesh:
+    lo = heightfield(N, A, J, f_lo, f_hi, seed_bottom)
+    hi = heightfield(N, A, J, f_lo, f_hi, seed_top)
+    P_hi = hi.P.copy()
+    P_hi[:, 2] = gap - P_hi[:, 2]
+    # heightfield normals are (-h_x, -h_y, 1)/|.|; the downward normal of z = gap - h is (-h_x, -h_y, -1)/|.|
+    N_hi = hi.N * np.array([1.0, 1.0, -1.0])
+    tri_hi = hi.tri[:, [0, 2, 1]] + lo.nv   # counter-clockwise seen from below
+    return Mesh(np.concatenate([lo.P, P_hi]), np.concatenate([lo.N, N_hi]),
+                np.concatenate([lo.tri, tri_hi]).astype(np.int32))
+
+
 # ---------------------------------------------------------------- workloads
 
 def points_uniform(n: int, lo: float, hi: float, z: float, seed: int) -> np.ndarray:
@@ -196,6 +214,7 @@ GLINTS_LARGE_LIGHT = np.asarray([[0.0, 0.0, 4.0]])
 
 CAUSTIC_LIGHT_OUTSIDE = np.asarray([[0.1, 0.05, 1.5]])
 CAUSTIC_LIGHT_INSIDE = np.asarray([[0.0, 0.0, 0.1]])
+MIRROR_GAP_LIGHT = np.asarray([[0.15, -0.1, 0.5]])
 
 
 def _euler(a: float, b: float, c: float) -> np.ndarray:

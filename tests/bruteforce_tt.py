@@ -1,14 +1,16 @@
-"""Brute-force search for two-vertex refraction paths (x0 -> T1 -> T2 -> x3),
-independent of the polynomial method.
+"""Brute-force search for two-vertex specular paths (x0 -> T1 -> T2 -> x3,
+reflection or refraction at each vertex), independent of the polynomial method.
 
 Unknowns z = (u1, v1, u2, v2): barycentric coordinates on both triangles, with
 interpolated normals.  The path-space constraints of Eq. (eq_ch) hold at both
 vertices: G_i = h_i^ x n_i^ = 0 with h_i = eta_in w_in + eta_out w_out (unit
 directions towards the neighbours).  Damped Gauss-Newton on the six residual
 components from many seeds: a grid over T1, each seed completed by tracing the
-exactly refracted ray into T2's plane (Snell's law in vector form), plus the
-local minima of the traced residual on a fine grid.  Converged points that are
-inside both (closed) triangles and refract at both vertices are the paths.
+exactly reflected or refracted ray into T2's plane (the laws in vector form),
+plus the local minima of the traced residual on a fine grid.  Converged points
+that are inside both (closed) triangles and have the right sides at both
+vertices (reflection: both neighbours on one side; refraction: opposite sides)
+are the paths.
 """
 from __future__ import annotations
 
@@ -40,18 +42,23 @@ def residual(T1P, T1N, T2P, T2N, x0, x3, eta, z):
     return G, side
 
 
-def _refract_into(T1P, T1N, T2P, x0, eta, u1, v1):
-    """(u2, v2) where the exactly refracted ray from x1(u1, v1) meets T2's plane."""
+def _refract_into(T1P, T1N, T2P, x0, eta, u1, v1, ev1="T"):
+    """(u2, v2) where the exactly reflected (ev1 = "R") or refracted ray from
+    x1(u1, v1) meets T2's plane."""
     x1 = _interp(T1P, u1, v1)
     n = _nz(_interp(T1N, u1, v1))
     d = _nz(x1 - x0)
     c = np.sum(d * n, -1)
-    n = np.where((c > 0)[..., None], -n, n)
-    ci = np.abs(c)
-    r = eta[0] / eta[1]
-    k = 1.0 - r * r * (1.0 - ci * ci)
-    ok = k >= 0
-    t = r * d + (r * ci - np.sqrt(np.maximum(k, 0.0)))[..., None] * n
+    if ev1 == "R":
+        t = d - (2.0 * c)[..., None] * n
+        ok = np.ones(c.shape, dtype=bool)
+    else:
+        n = np.where((c > 0)[..., None], -n, n)
+        ci = np.abs(c)
+        r = eta[0] / eta[1]
+        k = 1.0 - r * r * (1.0 - ci * ci)
+        ok = k >= 0
+        t = r * d + (r * ci - np.sqrt(np.maximum(k, 0.0)))[..., None] * n
     p0 = T2P[..., 0, :]
     e1, e2 = T2P[..., 1, :] - p0, T2P[..., 2, :] - p0
     m = np.cross(e1, e2)
@@ -99,10 +106,10 @@ def _gauss_newton(f, z, iters=50, h=1e-7):
 
 
 def solve_many(mesh_P, mesh_N, tri, x0, x3, t1, t2, eta=(1.0, 1.5, 1.0), seeds=10, grid=100, tol=1e-11,
-               dedup=1e-7):
-    """All refraction paths of every tuple (t1[k], t2[k]) between the points x0
-    and x3: a list with one [m, 4] array of (u1, v1, u2, v2) per tuple, sorted
-    by (v1, u1)."""
+               dedup=1e-7, chain="TT"):
+    """All paths of the given chain ("RR", "RT", "TR", "TT") of every tuple
+    (t1[k], t2[k]) between the points x0 and x3: a list with one [m, 4] array
+    of (u1, v1, u2, v2) per tuple, sorted by (v1, u1)."""
     t1 = np.asarray(t1)
     t2 = np.asarray(t2)
     nt = len(t1)
@@ -118,7 +125,7 @@ def solve_many(mesh_P, mesh_N, tri, x0, x3, t1, t2, eta=(1.0, 1.5, 1.0), seeds=1
     U, V = np.meshgrid(g, g, indexing="ij")
     for k in range(nt):
         sl = (slice(k, k + 1),)
-        u2, v2, ok = _refract_into(T1P[k], T1N[k], T2P[k], x0, eta, GU, GV)
+        u2, v2, ok = _refract_into(T1P[k], T1N[k], T2P[k], x0, eta, GU, GV, chain[0])
         G, _ = residual(T1P[k], T1N[k], T2P[k], T2N[k], x0, x3, eta, np.stack([GU, GV, u2, v2], -1))
         r = np.where(ok, np.linalg.norm(G[..., 3:], axis=-1), np.inf)
         inner = r[1:-1, 1:-1]
@@ -138,7 +145,7 @@ def solve_many(mesh_P, mesh_N, tri, x0, x3, t1, t2, eta=(1.0, 1.5, 1.0), seeds=1
     su = np.concatenate(su)
     sv = np.concatenate(sv)
     A1P, A1N, A2P, A2N = T1P[rows], T1N[rows], T2P[rows], T2N[rows]
-    u2, v2, ok = _refract_into(A1P, A1N, A2P, x0, eta, su, sv)
+    u2, v2, ok = _refract_into(A1P, A1N, A2P, x0, eta, su, sv, chain[0])
     rows, A1P, A1N, A2P, A2N = rows[ok], A1P[ok], A1N[ok], A2P[ok], A2N[ok]
     z = np.stack([su, sv, u2, v2], -1)[ok]
     out = [np.zeros((0, 4)) for _ in range(nt)]
@@ -151,7 +158,8 @@ def solve_many(mesh_P, mesh_N, tri, x0, x3, t1, t2, eta=(1.0, 1.5, 1.0), seeds=1
     z = _gauss_newton(f, z)
     G, side = f(z)
     res = np.linalg.norm(G, axis=-1)
-    keep = (res < tol) & np.all(side < 0, -1)
+    want = np.array([1.0 if c == "R" else -1.0 for c in chain])
+    keep = (res < tol) & np.all(side * want > 0, -1)
     e = 1e-12
     keep &= (z[:, 0] >= -e) & (z[:, 1] >= -e) & (z[:, 0] + z[:, 1] <= 1 + e)
     keep &= (z[:, 2] >= -e) & (z[:, 3] >= -e) & (z[:, 2] + z[:, 3] <= 1 + e)

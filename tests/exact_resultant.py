@@ -55,3 +55,40 @@ def udeg(C: np.ndarray) -> int:
     """Highest power of u with a nonzero coefficient row."""
     rows = np.nonzero(np.any(C != 0.0, axis=1))[0]
     return int(rows.max()) if len(rows) else 0
+
+
+def window_sign_hp(A: np.ndarray, B: np.ndarray, ma: int, nb: int, v: float, lo: float = -1.0, hi: float = 2.0,
+                   dps: int = 60):
+    """Product of sgn b(alpha, v) over the real roots alpha of a(., v) in
+    [lo, hi], from the exact values of the FP64 coefficients, with roots and
+    values to `dps` digits (mpmath).  None when a root lies within 1e-9 of an
+    end of the window (a crossing the sample cannot resolve)."""
+    import mpmath as mp
+
+    with mp.workdps(dps):
+        fv = Fraction(v)
+        mv = mp.mpf(fv.numerator) / fv.denominator
+
+        def coeffs(C, deg):
+            out = []
+            for i in range(deg + 1):
+                s = mp.mpf(0)
+                for j in range(C.shape[1] - i):
+                    if C[i, j] != 0.0:
+                        s += mp.mpf(float(C[i, j])) * mv ** j
+                out.append(s)
+            return out
+
+        ac, bc = coeffs(A, ma), coeffs(B, nb)
+        rts = mp.polyroots(list(reversed(ac)), maxsteps=500, extraprec=4 * dps)
+        tiny = mp.mpf(10) ** (-dps // 2)
+        sign = 1
+        for r in rts:
+            if abs(mp.im(r)) > tiny * max(1, abs(r)):
+                continue
+            x = mp.re(r)
+            if min(abs(x - lo), abs(x - hi)) < 1e-9:
+                return None
+            if lo <= x <= hi and mp.polyval(list(reversed(bc)), x) < 0:
+                sign = -sign
+        return sign

@@ -198,4 +198,34 @@ def test_mixed_2m_instances_graph_vs_separate_and_oracle(sp):
     st = parity.compare_onebounce(g1, orc, diag, len(smp), **parity.FP32)
     print("mixed 2M: paths", len(got), "R sample vs oracle", st, flush=True)
     assert st["compared"] > 20
+    # two-vertex part against the FP64 oracle: every tuple with a GPU path plus a seeded sample of 20000
+    g2 = got[got["query"] >= len(i1)].copy()
+    g2["query"] -= len(i1)
+    q0h, q3h, qth = Q2.q0.cpu().numpy(), Q2.q3.cpu().numpy(), Q2.qt.cpu().numpy().reshape(-1, 2)
+    smp2 = np.union1d(np.unique(g2["query"]), np.random.default_rng(45).choice(len(i2), 20000, replace=False))
+    o2, _ = oracle.solve_tt(sph.P, sph.N, sph.tri, scenes.caustic_receivers(), scenes.CAUSTIC_LIGHT_OUTSIDE,
+                            q0h[smp2], q3h[smp2], qth[smp2, 0], qth[smp2, 1])
+    pos = np.searchsorted(smp2, g2["query"])
+    g2["query"] = pos
+    n2 = _compare_tt_sets(g2, o2, len(smp2))
+    print("mixed 2M: TT sample vs oracle: tuples", len(smp2), "paths compared", n2, flush=True)
+    assert n2 >= 10
     ctx.close()
+
+
+def _compare_tt_sets(g, o, nq, tol=1e-10, band=1e-9, tau=1e-6):
+    bad = np.zeros(nq, dtype=bool)
+    bad[o["query"][(o["edge"] < band) | ((o["residual"] > tau / 10) & (o["residual"] < 10 * tau))]] = True
+    bad[g["query"][(g["edge"] < band) | ((g["residual"] > tau / 10) & (g["residual"] < 10 * tau))]] = True
+    g = g[~bad[g["query"]]]
+    o = o[~bad[o["query"]]]
+    g = g[np.lexsort((g["u"][:, 0], g["v"][:, 0], g["query"]))]
+    o = o[np.lexsort((o["u1"], o["v1"], o["query"]))]
+    gq, oq = np.bincount(g["query"], minlength=nq), np.bincount(o["query"], minlength=nq)
+    mism = np.nonzero(gq != oq)[0]
+    assert len(mism) == 0, f"{len(mism)} tuples differ: q={mism[:5]} gpu={gq[mism[:5]]} oracle={oq[mism[:5]]}"
+    if len(g):
+        err = max(np.abs(g["u"][:, 0] - o["u1"]).max(), np.abs(g["v"][:, 0] - o["v1"]).max(),
+                  np.abs(g["u"][:, 1] - o["u2"]).max(), np.abs(g["v"][:, 1] - o["v2"]).max())
+        assert err <= tol, err
+    return len(o)

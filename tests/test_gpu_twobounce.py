@@ -29,13 +29,16 @@ def _tag(name):
     print(f"[gpu-case] {name}", flush=True)
 
 
-def _gpu_tt(sp, ctx, mesh, x0s, x3s, q0, q3, qt, eta=(1.0, 1.5, 1.0)):
+def _gpu_tt(sp, ctx, mesh, x0s, x3s, q0, q3, qt, eta=(1.0, 1.5, 1.0), diag=False):
     dm = sp.DeviceMesh(mesh.P, mesh.N, mesh.tri)
     d0, d3 = sp.DevicePoints(x0s), sp.DevicePoints(x3s)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).cuda()  # noqa: E731
     cnt = torch.zeros(4, dtype=torch.int64, device="cuda")
-    s = ctx.solve_2bounce(dm, d0, d3, t(q0), t(q3), t(qt), eta, counters=cnt)
+    dq = torch.zeros(2 * len(q0), dtype=torch.int32, device="cuda") if diag else None
+    s = ctx.solve_2bounce(dm, d0, d3, t(q0), t(q3), t(qt), eta, counters=cnt, diag=dq)
     torch.cuda.synchronize()
+    if diag:
+        return s, cnt.cpu().numpy(), dq.cpu().numpy().reshape(-1, 2)
     return s, cnt.cpu().numpy()
 
 
@@ -92,6 +95,36 @@ def test_tt_random_culled_tuples_parity(sp, ctx):
     g, cnt = _gpu_tt(sp, ctx, mesh, x0s, x3, q0, q3, qt)
     n, nb = _compare_tt(g, o, len(q0))
     print("random tt compared", n, "excluded", nb, "sign changes oracle/gpu", od["n_vroots"].sum(), cnt[0])
+    # random culled tuples rarely hold a path: every tuple's (empty or not) set is compared
+    assert len(q0) - nb >= 0.99 * len(q0)
+
+
+def test_tt_traced_receivers_parity(sp, ctx):
+    """64 receivers where traced rays through the exact sphere land; the tuples
+    within 0.06 of each path's entry and exit: at least 50 compared paths,
+    sign-change counts per tuple compared as a diagnostic."""
+    _tag("tt 64 traced receivers")
+    mesh = scenes.caustic_sphere()
+    x3 = scenes.CAUSTIC_LIGHT_OUTSIDE
+    g = np.linspace(-0.35, 0.35, 8)
+    x0s, Q = [], []
+    for ox in g:
+        for oy in g:
+            x0, entry, exit_ = ttcases.traced_receiver((ox, oy, 0.0))
+            tp = ttcases.tuples_near(mesh, x0, x3[0], entry, exit_, 0.06)
+            Q.append(np.column_stack([np.full(len(tp), len(x0s)), tp]))
+            x0s.append(x0)
+    x0s = np.asarray(x0s)
+    Q = np.concatenate(Q).astype(np.int32)
+    z = np.zeros(len(Q), dtype=np.int32)
+    o, od = oracle.solve_tt(mesh.P, mesh.N, mesh.tri, x0s, x3, Q[:, 0], z, Q[:, 1], Q[:, 2])
+    gs, cnt, dq = _gpu_tt(sp, ctx, mesh, x0s, x3, Q[:, 0], z, Q[:, 1:], diag=True)
+    n, nb = _compare_tt(gs, o, len(Q))
+    rec = len(np.unique(Q[o["query"], 0]))
+    same = int(np.sum(dq[:, 0] == od["n_vroots"]))
+    print(f"{len(Q)} tuples of {len(x0s)} receivers: compared {n} paths ({rec} receivers), excluded {nb}; "
+          f"sign changes oracle {od['n_vroots'].sum()} gpu {dq[:, 0].sum()}, equal on {same} tuples")
+    assert n >= 50 and rec >= 20
 
 
 def test_tt_light_inside_sphere_has_no_paths(sp, ctx):

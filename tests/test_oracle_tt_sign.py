@@ -2,16 +2,18 @@
 
 det R(v) of the Bezout matrix (Eq. eq_bezout) equals, up to a constant factor
 and a power of lc_u(b), the resultant Res_u(a, b) (Sec. 5.1), whose sign is what
-the bisection of Sec. 5.2 tracks.  The oracle's default evaluates that sign by
-the resultant's product formula over the real roots of a(., v).  These tests
-compare it with the EXACT sign of the Sylvester resultant of the same FP64
-coefficients (exact rational arithmetic, tests/exact_resultant.py): on curved
-sphere tuples around traced caustic paths and on random systems up to degrees
-(16, 40), the ratio of the two signs must be one constant per system.  They
-also check that Gaussian elimination on the numeric Bezout matrix (the paper's
-literal procedure, det_method 0) and the product formula give the same valid
-paths where elimination is well conditioned (flat parallel slab), and record
-how the two compare on the sphere.
+the bisection of Sec. 5.2 tracks.  The resultant's product formula gives that
+sign as the product of sgn b over the real roots of a(., v) (det_method 1).
+These tests compare it with the EXACT sign of the Sylvester resultant of the
+same FP64 coefficients (exact rational arithmetic, tests/exact_resultant.py):
+on curved sphere tuples around traced caustic paths and on random systems up
+to degrees (16, 40), the ratio of the two signs must be one constant per
+system.  The oracle's default (det_method 2) restricts the product to roots
+with u in [-1, 2]; it is pinned against a 60-digit evaluation in
+test_oracle_2v_pins.py.  They also check that Gaussian elimination on the
+numeric Bezout matrix (the paper's literal procedure, det_method 0) and the
+product formulas give the same valid paths where elimination is well
+conditioned (flat parallel slab), and record how they compare on the sphere.
 """
 import numpy as np
 import pytest
@@ -126,10 +128,11 @@ def test_det_methods_agree_on_flat_slab(seed):
     N = np.array([[0, 0, -1.0]] * 3 + [[0, 0, 1.0]] * 3)
     tri = np.array([[0, 1, 2], [3, 4, 5]], dtype=np.int32)
     s0, d0 = oracle.solve_tt(P, N, tri, x0[None], x3[None], [0], [0], [0], [1], params=_params(0))
-    s1, d1 = oracle.solve_tt(P, N, tri, x0[None], x3[None], [0], [0], [0], [1], params=_params(1))
-    assert len(s0) == len(s1) == 1
-    for k in ("u1", "v1", "u2", "v2"):
-        assert abs(s0[k][0] - s1[k][0]) < 1e-12
+    for m in (1, 2):
+        s1, d1 = oracle.solve_tt(P, N, tri, x0[None], x3[None], [0], [0], [0], [1], params=_params(m))
+        assert len(s0) == len(s1) == 1
+        for k in ("u1", "v1", "u2", "v2"):
+            assert abs(s0[k][0] - s1[k][0]) < 1e-12
 
 
 def test_det_methods_on_sphere_neighbourhood():
@@ -144,10 +147,12 @@ def test_det_methods_on_sphere_neighbourhood():
     args = (mesh.P, mesh.N, mesh.tri, x0[None], x3[None], np.zeros(n), np.zeros(n), tup[:, 0], tup[:, 1])
     s0, d0 = oracle.solve_tt(*args, params=_params(0))
     s1, d1 = oracle.solve_tt(*args, params=_params(1))
-    print(f"{n} tuples: sign changes GE {d0['n_vroots'].sum()} product {d1['n_vroots'].sum()}; "
-          f"valid GE {len(s0)} product {len(s1)}")
+    s2, d2 = oracle.solve_tt(*args, params=_params(2))
+    print(f"{n} tuples: sign changes GE {d0['n_vroots'].sum()} product {d1['n_vroots'].sum()} "
+          f"windowed {d2['n_vroots'].sum()}; valid GE {len(s0)} product {len(s1)} windowed {len(s2)}")
     assert len(s1) >= 1
     k0 = {(int(s['query']), round(s['u1'], 8), round(s['v1'], 8)) for s in s0}
     k1 = {(int(s['query']), round(s['u1'], 8), round(s['v1'], 8)) for s in s1}
-    assert k0 == k1
+    k2 = {(int(s['query']), round(s['u1'], 8), round(s['v1'], 8)) for s in s2}
+    assert k0 == k1 == k2
     assert d0["n_vroots"].sum() > d1["n_vroots"].sum()
