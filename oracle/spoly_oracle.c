@@ -51,8 +51,8 @@ typedef struct {
     int32_t bisect_iters;/* bisection steps per sign change (10)                        */
     int32_t det_method;  /* sign of det R(v): 0 Gaussian elimination on the Bezout matrix, */
                          /* 1 product formula over the real roots of a(.,v),             */
-                         /* 2 the same product over the real roots in the window         */
-                         /*   u in [-1, 2] (the two-vertex default)                      */
+                         /* 2 the same product with factors below their rounding scale    */
+                         /*   counted as zero (the two-vertex default)                   */
 } or_params;
 
 typedef struct {
@@ -933,19 +933,17 @@ static int res_sign_product(arena *A, bp a, int ma, bp b, int n, double v)
     return sign;
 }
 
-/* Windowed product sign: the product of sgn b(alpha, v) over the real roots
- * alpha of a(., v) with u in [-1, 2], the triangle and one triangle width
- * around it.  Reading (two vertices): the full product of res_sign_product
- * also multiplies in roots of a far outside T1 (where the direction x1 -> x2
- * turns parallel to T2's plane, x2 goes to infinity and a and b nearly share a
- * root), and there the FP64 value of b is rounding noise whose sign flips from
- * one v to the next.  A root of the window contributes the same factor to both
- * functions, so every sign change of the full product that comes from a root
- * of the resultant with u in the window, every physical solution among them,
- * is a sign change of this one too.  The windowed product also changes sign
- * where a root crosses u = -1 or u = 2 with b < 0 there; the v it yields has
- * no admissible u and the path phase rejects it.                             */
-static int res_sign_window(arena *A, bp a, int ma, bp b, double v)
+/* Conditioned product sign (det_method 2, the two-vertex default): the product
+ * formula of res_sign_product, where a factor b(alpha, v) whose magnitude does
+ * not exceed 1e-11 of sum_i |b_i(v)| |alpha|^i counts as zero, and
+ * sgn(0) := +1.  Reading: rounding makes such a value's sign arbitrary (its
+ * Horner error bound is ~1e-14 of that sum), and it does occur away from any
+ * solution: where the direction x1 -> x2 turns parallel to T2's plane (x2 at
+ * infinity) a and b nearly share a root, a(., v) has a near-double real pair far
+ * outside T1, and the FP64 values of b there flip sign from one v to the next
+ * (their 60-digit values do not).  Near a physical solution the rule only moves
+ * the sign change by ~1e-11 of the value's scale.                           */
+static int res_sign_cond(arena *A, bp a, int ma, bp b, double v)
 {
     size_t mark = A->top;
     double *ai = (double *)ar_alloc(A, sizeof(double) * (size_t)(ma + 1));
@@ -961,12 +959,23 @@ static int res_sign_window(arena *A, bp a, int ma, bp b, double v)
         bi[i] = s;
     }
     int sign = 1;
+    if (ai[ma] == 0.0) { A->top = mark; return 1; }
+    double B = 0.0;
+    for (int k = 1; k <= ma; ++k) B = fmax(B, pow(fabs(ai[ma - k] / ai[ma]), 1.0 / k));
+    B = 2.0 * B;
+    if (!(B > 0.0)) B = 1.0;
+    double *w = (double *)ar_alloc(A, sizeof(double) * (size_t)(ma + 1));
+    double pw = 1.0;
+    for (int k = 0; k <= ma; ++k) { w[k] = ai[k] * pw; pw *= B; }
     double roots[64];
-    int nr = isolate(A, ai, ma, -1.0, 2.0, roots, 64);
+    int nr = isolate(A, w, ma, -1.0, 1.0, roots, 64);
     for (int k = 0; k < nr; ++k) {
-        double s = 0.0;
-        for (int i = b.d; i >= 0; --i) s = s * roots[k] + bi[i];
-        if (s < 0.0) sign = -sign;
+        double al = roots[k] * B, s = 0.0, m = 0.0;
+        for (int i = b.d; i >= 0; --i) {
+            s = s * al + bi[i];
+            m = m * fabs(al) + fabs(bi[i]);
+        }
+        if (s < 0.0 && fabs(s) > 1e-11 * m) sign = -sign;
     }
     A->top = mark;
     return sign;
@@ -989,7 +998,7 @@ static void solve_2v(arena *A, const tri_t *T1, const tri_t *T2, v3 x0, v3 x3, c
     /* piecewise sign scan of det R(v) on [0,1] */
     int P = prm->pieces;
     int *sg = (int *)ar_alloc(A, sizeof(int) * (size_t)(P + 1));
-#define DETSIGN(vv) (prm->det_method == 2 ? res_sign_window(A, a, ma, b, (vv)) : \
+#define DETSIGN(vv) (prm->det_method == 2 ? res_sign_cond(A, a, ma, b, (vv)) : \
                      prm->det_method == 1 ? res_sign_product(A, a, ma, b, n, (vv)) : det_sign_at(A, a, b, n, (vv)))
     for (int j = 0; j <= P; ++j) sg[j] = DETSIGN((double)j / P);
     double vr[OR_MAXSOL * 8];
@@ -1129,14 +1138,14 @@ int or_res_sign(const double *a_in, int32_t da, const double *b_in, int32_t db, 
     return s;
 }
 
-/* windowed product sign (det_method 2) for given bivariate a, b */
-int or_res_sign_window(const double *a_in, int32_t da, const double *b_in, int32_t db, int32_t ma, double v)
+/* conditioned product sign (det_method 2) for given bivariate a, b */
+int or_res_sign_cond(const double *a_in, int32_t da, const double *b_in, int32_t db, int32_t ma, double v)
 {
     arena A; A.cap = (size_t)16 << 20; A.top = 0; A.base = (char *)malloc(A.cap);
     bp a = bp_new(&A, da), b = bp_new(&A, db);
     memcpy(a.c, a_in, sizeof(double) * (size_t)(da + 1) * (size_t)(da + 1));
     memcpy(b.c, b_in, sizeof(double) * (size_t)(db + 1) * (size_t)(db + 1));
-    int s = res_sign_window(&A, a, ma, b, v);
+    int s = res_sign_cond(&A, a, ma, b, v);
     free(A.base);
     return s;
 }

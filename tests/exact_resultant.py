@@ -57,12 +57,12 @@ def udeg(C: np.ndarray) -> int:
     return int(rows.max()) if len(rows) else 0
 
 
-def window_sign_hp(A: np.ndarray, B: np.ndarray, ma: int, nb: int, v: float, lo: float = -1.0, hi: float = 2.0,
-                   dps: int = 60):
-    """Product of sgn b(alpha, v) over the real roots alpha of a(., v) in
-    [lo, hi], from the exact values of the FP64 coefficients, with roots and
-    values to `dps` digits (mpmath).  None when a root lies within 1e-9 of an
-    end of the window (a crossing the sample cannot resolve)."""
+def cond_sign_hp(A: np.ndarray, B: np.ndarray, ma: int, nb: int, v: float, rel: float = 1e-11, dps: int = 60):
+    """Product of sgn b(alpha, v) over the real roots alpha of a(., v), where a
+    factor with |b(alpha)| <= rel * sum_i |b_i| |alpha|^i counts as +1, from the
+    exact values of the FP64 coefficients, with roots and values to `dps`
+    digits (mpmath).  None when a factor's ratio lies within a factor 30 of
+    `rel` (too close to the rule's threshold for a sample to decide)."""
     import mpmath as mp
 
     with mp.workdps(dps):
@@ -87,8 +87,11 @@ def window_sign_hp(A: np.ndarray, B: np.ndarray, ma: int, nb: int, v: float, lo:
             if abs(mp.im(r)) > tiny * max(1, abs(r)):
                 continue
             x = mp.re(r)
-            if min(abs(x - lo), abs(x - hi)) < 1e-9:
+            val = mp.polyval(list(reversed(bc)), x)
+            scale = mp.polyval([abs(c) for c in reversed(bc)], abs(x))
+            ratio = abs(val) / scale if scale > 0 else mp.mpf(0)
+            if rel / 30 < ratio < rel * 30:
                 return None
-            if lo <= x <= hi and mp.polyval(list(reversed(bc)), x) < 0:
+            if val < 0 and ratio > rel:
                 sign = -sign
         return sign

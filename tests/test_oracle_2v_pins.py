@@ -202,22 +202,22 @@ def test_neighbourhoods_match_bruteforce(chain):
 
 
 @pytest.mark.parametrize("chain", ["RR", "RT", "TR", "TT"])
-def test_window_sign_matches_high_precision(chain):
-    """The two-vertex det sign (product of sgn b over the real roots of a(., v)
-    with u in [-1, 2]) equals the same product taken with the roots and values
-    of the FP64 coefficients computed to 60 digits, at every sample."""
+def test_cond_sign_matches_high_precision(chain):
+    """The two-vertex det sign (product of sgn b over the real roots of a(., v),
+    factors within 1e-11 of their rounding scale counted as +1) equals the
+    same product taken with the roots and values of the FP64 coefficients
+    computed to 60 digits, at every sample."""
     mesh, x0, x3, t1, t2, _ = tc.trace_paths(chain, 3, 31)
     eta = tc.SETUPS[chain][2]
     checked = 0
     for k in range(len(t1)):
-        for nb_tuple in ((t1[k], t2[k]), (t1[k], t2[(k + 1) % len(t2)])):
-            A, B, n, _ = oracle.coeffs_2v(mesh.P, mesh.N, mesh.tri, nb_tuple[0], nb_tuple[1], x0[k], x3[k], chain,
-                                          eta)
+        for pair in ((t1[k], t2[k]), (t1[k], t2[(k + 1) % len(t2)])):
+            A, B, n, _ = oracle.coeffs_2v(mesh.P, mesh.N, mesh.tri, pair[0], pair[1], x0[k], x3[k], chain, eta)
             ma, nb = er.udeg(A), er.udeg(B)
             for v in [round((j + 0.5) / 12 * 4096) / 4096 for j in range(12)]:
-                ref = er.window_sign_hp(A, B, ma, nb, v)
+                ref = er.cond_sign_hp(A, B, ma, nb, v)
                 if ref is None:
                     continue
-                assert oracle.res_sign_window(A, B, ma, v) == ref, (chain, k, v)
+                assert oracle.res_sign_cond(A, B, ma, v) == ref, (chain, k, v)
                 checked += 1
     assert checked >= 60
