@@ -202,17 +202,19 @@ spoly_status spoly_cull_2bounce(spoly_ctx *ctx, const spoly_mesh *mesh,
 
 /*
  * Full solve for k = 2 specular vertices (Sec. 4.4-4.5, Sec. 5.2): chain [host, k]
- * must be {SPOLY_T, SPOLY_T}; eta [host, k+1] = IORs of the segments x0x1,
- * x1x2, x2x3 (Eq. eq_ch).  Query q solves x0s[q_x0[q]] -> triangle q_tris[2q]
- * -> triangle q_tris[2q+1] -> x3s[q_x3[q]].
- * The refracted direction at x1 uses the piecewise (1,1)-rational square root of
- * Sec. 4.4: sqrt_table [host, optional] = 7 piece ends then (c0, c1, d0, d1)
- * for each of the 6 pieces; NULL selects the library's minimax table.  The
- * sign of det R(v) is sampled at v = j/pieces (pieces <= 127) and each sign
- * change is refined to 2^-bisect_iters of its width (bisect_iters <= 10, the
- * dyadic lattice of that many bisection steps, searched in two wave-wide
- * rounds); every candidate is polished in FP64 on
- * the exact refraction constraints (the approximation only brackets roots).
+ * = the event at T1 then at T2, each SPOLY_R or SPOLY_T (chains RR, RT, TR,
+ * TT); eta [host, k+1] = IORs of the segments x0x1, x1x2, x2x3 (Eq. eq_ch); a
+ * reflection needs equal IORs on its two segments (else E_INVALID_ARG).
+ * Query q solves x0s[q_x0[q]] -> triangle q_tris[2q] -> triangle q_tris[2q+1]
+ * -> x3s[q_x3[q]].
+ * A reflected direction at x1 is exact (Eq. eq_431_di scaled by |n|^2); a
+ * refracted one uses the piecewise (1,1)-rational square root of Sec. 4.4:
+ * sqrt_table [host, optional] = 7 piece ends then (c0, c1, d0, d1) for each
+ * of the 6 pieces; NULL selects the library's minimax table.  The sign of
+ * det R(v) is sampled at v = j/pieces (1 <= pieces <= 4095) and each sign
+ * change is refined by bisect_iters (<= 40) bisection steps; near-double root
+ * pairs of a(., v) are left out of the sign's product.  Every candidate is polished
+ * in FP64 on the exact constraints (the approximation only brackets roots).
  * prec must be SPOLY_FP64.  Records carry tri[0..1] and (u,v) of both vertices.
  * counters / diag_q as for spoly_solve_1bounce ([0] counts sign changes).
  */

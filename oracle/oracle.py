@@ -39,7 +39,7 @@ def default_params(two_bounce: bool = False) -> Params:
     bisection steps (Sec. 5.2); u searched on [-m, 1-v+m] before polish with
     m = 1e-4 (one bounce) or 0.05 (two bounces, whose approximate roots can sit
     up to ~1e-2 away from the exact ones); up to 6 Newton steps; two vertices
-    take the sign of det R(v) from the conditioned product formula (det_method 2)."""
+    take the sign of det R(v) from the paired product formula (det_method 2)."""
     return Params(1e-6, 0.05 if two_bounce else 1e-4, 1e-8, 6, 100, 10, 2 if two_bounce else 0)
 
 
@@ -72,7 +72,7 @@ def lib():
         L.or_isolate.argtypes = [P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, P, ctypes.c_int32]
         L.or_det_sign.argtypes = [P, ctypes.c_int32, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double]
         L.or_res_sign.argtypes = [P, ctypes.c_int32, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double]
-        L.or_res_sign_cond.argtypes = [P, ctypes.c_int32, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double]
+        L.or_res_sign_paired.argtypes = [P, ctypes.c_int32, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double]
         L.or_maxsol.restype = ctypes.c_int
         L.or_cull_tt.argtypes = [P, P, P, ctypes.c_int64, P, ctypes.c_int64, P, ctypes.c_int64, P,
                                  ctypes.c_double, P]
@@ -275,14 +275,14 @@ def res_sign(A: np.ndarray, B: np.ndarray, ma: int, v: float) -> int:
     return int(L.or_res_sign(_p(A), A.shape[0] - 1, _p(B), B.shape[0] - 1, int(ma), v))
 
 
-def res_sign_cond(A: np.ndarray, B: np.ndarray, ma: int, v: float) -> int:
+def res_sign_paired(A: np.ndarray, B: np.ndarray, ma: int, v: float) -> int:
     """The two-vertex default (det_method 2): the product of sgn b(alpha, v)
-    over the real roots alpha of a(., v), a factor within 1e-11 of
-    sum_i |b_i| |alpha|^i counting as +1."""
+    over the real roots alpha of a(., v), two consecutive roots closer than
+    1e-4 max(1, |alpha|) left out."""
     L = lib()
     A = _c(A, np.float64)
     B = _c(B, np.float64)
-    return int(L.or_res_sign_cond(_p(A), A.shape[0] - 1, _p(B), B.shape[0] - 1, int(ma), v))
+    return int(L.or_res_sign_paired(_p(A), A.shape[0] - 1, _p(B), B.shape[0] - 1, int(ma), v))
 
 
 def cull_1bounce(P, N, tri, x0s, x2s, eta0=1.0, eta1=1.0, margin=0.0) -> np.ndarray:

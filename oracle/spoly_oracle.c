@@ -51,8 +51,8 @@ typedef struct {
     int32_t bisect_iters;/* bisection steps per sign change (10)                        */
     int32_t det_method;  /* sign of det R(v): 0 Gaussian elimination on the Bezout matrix, */
                          /* 1 product formula over the real roots of a(.,v),             */
-                         /* 2 the same product with factors below their rounding scale    */
-                         /*   counted as zero (the two-vertex default)                   */
+                         /* 2 the same product with near-double root pairs left out      */
+                         /*   (the two-vertex default)                                   */
 } or_params;
 
 typedef struct {
@@ -933,17 +933,16 @@ static int res_sign_product(arena *A, bp a, int ma, bp b, int n, double v)
     return sign;
 }
 
-/* Conditioned product sign (det_method 2, the two-vertex default): the product
- * formula of res_sign_product, where a factor b(alpha, v) whose magnitude does
- * not exceed 1e-11 of sum_i |b_i(v)| |alpha|^i counts as zero, and
- * sgn(0) := +1.  Reading: rounding makes such a value's sign arbitrary (its
- * Horner error bound is ~1e-14 of that sum), and it does occur away from any
- * solution: where the direction x1 -> x2 turns parallel to T2's plane (x2 at
- * infinity) a and b nearly share a root, a(., v) has a near-double real pair far
- * outside T1, and the FP64 values of b there flip sign from one v to the next
- * (their 60-digit values do not).  Near a physical solution the rule only moves
- * the sign change by ~1e-11 of the value's scale.                           */
-static int res_sign_cond(arena *A, bp a, int ma, bp b, double v)
+/* Paired product sign (det_method 2, the two-vertex default): the product
+ * formula of res_sign_product, where two consecutive real roots of a(., v)
+ * closer than 1e-4 max(1, |alpha|) contribute nothing.  Reading: such a pair
+ * contributes b(alpha1) b(alpha2) ~ b(alpha)^2 > 0 unless b vanishes between
+ * two nearly equal roots, and the pair does occur away from any solution:
+ * where the direction x1 -> x2 turns parallel to T2's plane (x2 at infinity)
+ * a(., v) has a near-double real pair far outside T1 at which b nearly vanishes
+ * too, and there the FP64 values of b are rounding noise whose signs flip from
+ * one v to the next (their 60-digit values do not).                        */
+static int res_sign_paired(arena *A, bp a, int ma, bp b, double v)
 {
     size_t mark = A->top;
     double *ai = (double *)ar_alloc(A, sizeof(double) * (size_t)(ma + 1));
@@ -970,12 +969,11 @@ static int res_sign_cond(arena *A, bp a, int ma, bp b, double v)
     double roots[64];
     int nr = isolate(A, w, ma, -1.0, 1.0, roots, 64);
     for (int k = 0; k < nr; ++k) {
-        double al = roots[k] * B, s = 0.0, m = 0.0;
-        for (int i = b.d; i >= 0; --i) {
-            s = s * al + bi[i];
-            m = m * fabs(al) + fabs(bi[i]);
-        }
-        if (s < 0.0 && fabs(s) > 1e-11 * m) sign = -sign;
+        double al = roots[k] * B;
+        if (k + 1 < nr && roots[k + 1] * B - al <= 1e-4 * fmax(1.0, fabs(al))) { ++k; continue; }
+        double s = 0.0;
+        for (int i = b.d; i >= 0; --i) s = s * al + bi[i];
+        if (s < 0.0) sign = -sign;
     }
     A->top = mark;
     return sign;
@@ -998,7 +996,7 @@ static void solve_2v(arena *A, const tri_t *T1, const tri_t *T2, v3 x0, v3 x3, c
     /* piecewise sign scan of det R(v) on [0,1] */
     int P = prm->pieces;
     int *sg = (int *)ar_alloc(A, sizeof(int) * (size_t)(P + 1));
-#define DETSIGN(vv) (prm->det_method == 2 ? res_sign_cond(A, a, ma, b, (vv)) : \
+#define DETSIGN(vv) (prm->det_method == 2 ? res_sign_paired(A, a, ma, b, (vv)) : \
                      prm->det_method == 1 ? res_sign_product(A, a, ma, b, n, (vv)) : det_sign_at(A, a, b, n, (vv)))
     for (int j = 0; j <= P; ++j) sg[j] = DETSIGN((double)j / P);
     double vr[OR_MAXSOL * 8];
@@ -1138,14 +1136,14 @@ int or_res_sign(const double *a_in, int32_t da, const double *b_in, int32_t db, 
     return s;
 }
 
-/* conditioned product sign (det_method 2) for given bivariate a, b */
-int or_res_sign_cond(const double *a_in, int32_t da, const double *b_in, int32_t db, int32_t ma, double v)
+/* paired product sign (det_method 2) for given bivariate a, b */
+int or_res_sign_paired(const double *a_in, int32_t da, const double *b_in, int32_t db, int32_t ma, double v)
 {
     arena A; A.cap = (size_t)16 << 20; A.top = 0; A.base = (char *)malloc(A.cap);
     bp a = bp_new(&A, da), b = bp_new(&A, db);
     memcpy(a.c, a_in, sizeof(double) * (size_t)(da + 1) * (size_t)(da + 1));
     memcpy(b.c, b_in, sizeof(double) * (size_t)(db + 1) * (size_t)(db + 1));
-    int s = res_sign_cond(&A, a, ma, b, v);
+    int s = res_sign_paired(&A, a, ma, b, v);
     free(A.base);
     return s;
 }

@@ -292,10 +292,15 @@ spoly_status spoly_solve_nbounce(spoly_ctx* ctx, const spoly_mesh* mesh, int32_t
     if (n_queries < 0 || out_capacity < 0 || (out_capacity > 0 && !out)) return SPOLY_E_INVALID_ARG;
     if (n_queries > 0 && (!q_x0 || !q_x3 || !q_tris)) return SPOLY_E_INVALID_ARG;
     if (k != 2) return SPOLY_E_UNSUPPORTED;
-    if (chain[0] != SPOLY_T || chain[1] != SPOLY_T) return SPOLY_E_UNSUPPORTED;
+    for (int i = 0; i < 2; ++i)
+        if (chain[i] != SPOLY_R && chain[i] != SPOLY_T) return SPOLY_E_INVALID_ARG;
     if (prec != SPOLY_FP64) return SPOLY_E_UNSUPPORTED;
     if (!(eta[0] > 0.0) || !(eta[1] > 0.0) || !(eta[2] > 0.0)) return SPOLY_E_INVALID_ARG;
-    if (params->pieces < 1 || params->pieces > 127 || params->bisect_iters < 0 || params->bisect_iters > 10 ||
+    // a reflection keeps its medium: equal IORs on its two segments
+    for (int i = 0; i < 2; ++i)
+        if (chain[i] == SPOLY_R && eta[i] != eta[i + 1]) return SPOLY_E_INVALID_ARG;
+    if (params->pieces < 1 || params->pieces > spoly::kMaxPieces || params->bisect_iters < 0 ||
+        params->bisect_iters > spoly::kMaxBisect ||
         params->polish_iters < 0 ||
         !(params->tau > 0.0) || !(params->u_margin >= 0.0) || !(params->dedup >= 0.0))
         return SPOLY_E_INVALID_ARG;
@@ -308,6 +313,7 @@ spoly_status spoly_solve_nbounce(spoly_ctx* ctx, const spoly_mesh* mesh, int32_t
     A.x3x = x3s->x; A.x3y = x3s->y; A.x3z = x3s->z;
     A.q_x0 = q_x0; A.q_x3 = q_x3; A.q_tris = q_tris;
     A.nq = n_queries;
+    A.ev1 = chain[0]; A.ev2 = chain[1];
     A.eta0 = eta[0]; A.eta1 = eta[1]; A.eta2 = eta[2];
     const double* tb = sqrt_table ? sqrt_table : nullptr;
     for (int i = 0; i < 7; ++i) A.sqrt_bp[i] = tb ? tb[i] : kSqrtPieceEnds[i];
@@ -448,7 +454,8 @@ extern "C" spoly_status spoly_solve_mixed(spoly_ctx* ctx, const spoly_mesh* mesh
     if (shape->workgroups_per_cu < 1 || shape->workgroups_per_cu > 32 || shape->r_tile < 64 ||
         shape->r_tile > 4096 || (shape->r_tile % 64) != 0 || shape->order < 0 || shape->order > 2)
         return SPOLY_E_INVALID_ARG;
-    if (params->pieces < 1 || params->pieces > 127 || params->bisect_iters < 0 || params->bisect_iters > 10 ||
+    if (params->pieces < 1 || params->pieces > spoly::kMaxPieces || params->bisect_iters < 0 ||
+        params->bisect_iters > spoly::kMaxBisect ||
         params->polish_iters < 0 || !(params->tau > 0.0) || !(params->iso_eps > 0.0) || !(params->u_margin >= 0.0) ||
         !(params->dedup >= 0.0))
         return SPOLY_E_INVALID_ARG;
@@ -483,6 +490,7 @@ extern "C" spoly_status spoly_solve_mixed(spoly_ctx* ctx, const spoly_mesh* mesh
     T.x3x = x3s2->x; T.x3y = x3s2->y; T.x3z = x3s2->z;
     T.q_x0 = q2_x0; T.q_x3 = q2_x3; T.q_tris = q2_tris;
     T.nq = n2;
+    T.ev1 = SPOLY_T; T.ev2 = SPOLY_T;
     T.eta0 = eta2[0]; T.eta1 = eta2[1]; T.eta2 = eta2[2];
     for (int i = 0; i < 7; ++i) T.sqrt_bp[i] = kSqrtPieceEnds[i];
     for (int i = 0; i < 24; ++i) T.sqrt_c[i] = kSqrtCoef[i];

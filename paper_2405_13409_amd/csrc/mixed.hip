@@ -35,6 +35,7 @@ __global__ void __launch_bounds__(64) k_mixed(MixedArgs M)
 {
     __shared__ double lds[kLdsDoubles];
     __shared__ TTGeo sgeo;
+    __shared__ unsigned long long smask[kSignWords], cmask[kSignWords];
     const int lane = lane_id();
     for (;;) {
         unsigned long long item = 0;
@@ -53,7 +54,7 @@ __global__ void __launch_bounds__(64) k_mixed(MixedArgs M)
                 onebounce_lane<R, EV>(M.r, q, q < b1, 0);
             }
         } else {
-            tt_tuple(M.t, idx, lds, &sgeo, M.r.nq);
+            tt_tuple(M.t, idx, lds, &sgeo, smask, cmask, M.r.nq);
         }
         __syncthreads();
     }

@@ -1,21 +1,24 @@
-// Two specular vertices with refraction at both (TT, Sec. 4.5): one wave per
+// Two specular vertices (Sec. 4.5: chains RR, RT, TR and TT): one wave per
 // (x0, T1, T2, x3) tuple.
 //   coefficient phase  (wave-cooperative, LDS): the coplanarity polynomial
-//       a(u,v) = (Dt x (x3 - x1)) . M2 of the mapped system (Eq. eq_rct,
-//       Eq. eq_refr_rational with the piecewise rational square root);
+//       a(u,v) = (Dt x (x3 - x1)) . M2 of the mapped system (Eq. eq_rct), with
+//       Dt the reflected direction (Eq. eq_431_di, scaled by |n1|^2) or the
+//       refracted one (Eq. eq_refr_rational with the piecewise rational square
+//       root);
 //   elimination + scan (lane per sample of v): the sign of det R(v) of the
 //       Bezout matrix (Eq. eq_bezout) at v_j = j/pieces, j = 0..pieces, and at
-//       the bisection midpoints (Sec. 5.2).  det R(v) = C Res_u(a, b)(v) with a
-//       constant C, and Res_u(a,b) = lc(a)^deg b prod_{a(alpha)=0} b(alpha);
-//       complex roots pair up into |b|^2 > 0, so the sign is the product of
-//       sgn b(alpha, v) over the real roots alpha of a(., v) (lc(a)^deg b > 0:
-//       deg_u b = 6D + 2 + 2 f2 is even).  Real roots come from the recursive
-//       isolation of Sec. 5.2 on Fujiwara's root bound; b is the square-form
-//       polynomial of Eq. eq_cpf_result, evaluated through its defining
-//       products of the mapped quantities.
-//   path phase (lane per v root): u from a(u)|_v, exact refraction at x1 and
-//       intersection with T2's plane, FP64 Newton polish on h2 x n2 = 0,
-//       validation at both vertices, wave-ballot compaction.
+//       the bisection midpoints (Sec. 5.2).  det R(v) = C lc(b)^k Res_u(a, b)(v),
+//       and Res_u(a,b) = lc(a)^deg b prod_{a(alpha)=0} b(alpha); complex roots
+//       pair up into |b|^2 > 0, so, up to a sign that is constant where lc_u(a)
+//       keeps its sign, it is the product of sgn b(alpha, v) over the real roots
+//       alpha of a(., v), near-double root pairs left out.  Real roots come from the
+//       recursive isolation of Sec. 5.2 on Fujiwara's root bound; b is the
+//       square-form (Eq. eq_cpf_result, refraction at x2) or product-form (Eq.
+//       eq_pf_result, reflection at x2) polynomial, evaluated through its
+//       defining products of the mapped quantities.
+//   path phase (lane per v root): u from a(u)|_v, exact reflection or
+//       refraction at x1 and intersection with T2's plane, FP64 Newton polish
+//       on h2 x n2 = 0, validation at both vertices, wave-ballot compaction.
 #include "spoly_dev.hpp"
 #include "twobounce.hpp"
 
@@ -33,6 +36,8 @@ struct TTGeo {
     double S, sq0, sq1, sr0, sr1, sg, sqrtS;    // square-root approximation of this tuple
     int axis;
     int f1, f2;                                 // 1 = interpolated normals, 0 = flat
+    int ev1, ev2;                               // SPOLY_R or SPOLY_T at x1, x2
+    V3<double> edge2;                           // product-form edge of T2 (reflection at x2)
 };
 
 __device__ __forceinline__ V3<double> ld3t(const double* x, const double* y, const double* z, int i)
@@ -52,6 +57,19 @@ __device__ __forceinline__ int tt_axis(V3<double> c, V3<double> xa, V3<double> x
     if (fabs(m.x) >= 0.5) return 0;
     if (fabs(m.z) >= 0.5) return 2;
     return 1;
+}
+
+// Product-form edge at x2: e21 unless it nearly lies in the incidence plane
+// (|e21^.m_c| < 1/4 and e22 does better), then e22.
+__device__ __forceinline__ V3<double> tt_edge(V3<double> c, V3<double> xa, V3<double> xb, V3<double> e1,
+                                              V3<double> e2)
+{
+    V3<double> m = cross(c - xa, xb - xa);
+    double l = len(m);
+    if (!(l > 0.0)) return e1;
+    m = m * (1.0 / l);
+    double g1 = fabs(dot(normalized(e1), m)), g2 = fabs(dot(normalized(e2), m));
+    return (g1 < 0.25 && g2 > g1) ? e2 : e1;
 }
 
 __device__ void tt_setup(const TTArgs& A, int64_t q, TTGeo& g)
@@ -95,6 +113,9 @@ __device__ void tt_setup(const TTArgs& A, int64_t q, TTGeo& g)
     g.sqrtS = sqrt(g.S);
     V3<double> c2 = g.p2 + g.e21 * (1.0 / 3.0) + g.e22 * (1.0 / 3.0);
     g.axis = tt_axis(c2, c1, g.x3);
+    g.ev1 = A.ev1;
+    g.ev2 = A.ev2;
+    g.edge2 = tt_edge(c2, c1, g.x3, g.e21, g.e22);
 }
 
 // ------------------------------------------------------------------ LDS bivariate polynomials (wave-cooperative)
@@ -168,7 +189,7 @@ constexpr int kLdsDoubles = 3 * sq(1) /*X1*/ + 3 * sq(1) /*N1*/ + 3 * sq(1) /*D0
 // Build a(u,v) into A (degree 2D + 1 + f2 <= 16); returns its structural degree.
 __device__ int tt_build_a(const TTGeo& g, double* lds, LP& Aout)
 {
-    const int D = 3 + 4 * g.f1;
+    const int D = g.ev1 == SPOLY_R ? 1 + 2 * g.f1 : 3 + 4 * g.f1;
     double* p = lds;
     auto take = [&](int d) { LP r{p, d}; p += sq(d); return r; };
     LP X1[3], N1[3], D0[3], Q[3], W[3];
@@ -215,6 +236,20 @@ __device__ int tt_build_a(const TTGeo& g, double* lds, LP& Aout)
         sync_wave();
     }
     LP nnS{NN.c, 2 * g.f1}, dnS{DN.c, 1 + g.f1};
+    LP dt[3];
+    if (g.ev1 == SPOLY_R) {
+        // reflected direction |n1|^2 d0 - 2 (d0.n1) n1
+        for (int k = 0; k < 3; ++k) {
+            dt[k] = LP{DT[k].c, D};
+            lp_zero(dt[k]);
+        }
+        sync_wave();
+        for (int k = 0; k < 3; ++k) {
+            lp_mul_acc(dt[k], nnS, D0[k], 1.0);
+            lp_mul_acc(dt[k], dnS, N1[k], -2.0);
+        }
+        sync_wave();
+    } else {
     const int db = 2 + 2 * g.f1;
     LP beta{BETA.c, db}, num{NUM.c, db}, den{DEN.c, db};
     lp_zero(beta);
@@ -232,7 +267,7 @@ __device__ int tt_build_a(const TTGeo& g, double* lds, LP& Aout)
     lp_addc(den, g.sr0);
     sync_wave();
     const int dt_ = 1 + 2 * g.f1;
-    LP tang[3], dt[3];
+    LP tang[3];
     for (int k = 0; k < 3; ++k) {
         tang[k] = LP{TANG[k].c, dt_};
         dt[k] = LP{DT[k].c, D};
@@ -250,6 +285,7 @@ __device__ int tt_build_a(const TTGeo& g, double* lds, LP& Aout)
         lp_mul_acc(dt[k], num, N1[k], g.sg * g.sqrtS);
     }
     sync_wave();
+    }
     // DXE = Dt x e22 (constant vector): linear combinations
     LP dxe[3];
     for (int k = 0; k < 3; ++k) {
@@ -440,16 +476,26 @@ __device__ __forceinline__ double tt_b_eval(const TTGeo& g, double u, double v)
     V3<double> x1 = g.p1 + g.e11 * u + g.e12 * v;
     V3<double> n1 = g.n10 + (g.dn11 * u + g.dn12 * v) * double(g.f1);
     V3<double> d0 = x1 - g.x0;
-    double nn = dot(n1, n1), dd = dot(d0, d0), dn = dot(d0, n1);
-    double beta = (1.0 - g.etap * g.etap) * nn * dd + g.etap * g.etap * dn * dn;
-    double num = g.sq0 + g.sq1 * beta / g.S, den = g.sr0 + g.sr1 * beta / g.S;
-    V3<double> Dt = (d0 * nn - n1 * dn) * (g.etap * den) + n1 * (g.sg * g.sqrtS * num);
+    double nn = dot(n1, n1), dn = dot(d0, n1);
+    V3<double> Dt;
+    if (g.ev1 == SPOLY_R) {
+        Dt = d0 * nn - n1 * (2.0 * dn);
+    } else {
+        double dd = dot(d0, d0);
+        double beta = (1.0 - g.etap * g.etap) * nn * dd + g.etap * g.etap * dn * dn;
+        double num = g.sq0 + g.sq1 * beta / g.S, den = g.sr0 + g.sr1 * beta / g.S;
+        Dt = (d0 * nn - n1 * dn) * (g.etap * den) + n1 * (g.sg * g.sqrtS * num);
+    }
     V3<double> q = x1 - g.p2;
     V3<double> dxe = cross(Dt, g.e22);
     double ut = dot(dxe, q), vt = dot(cross(q, g.e21), Dt), ka = dot(dxe, g.e21);
     V3<double> X2 = g.p2 * ka + g.e21 * ut + g.e22 * vt;
     V3<double> M2 = g.n20 * ka + (g.dn21 * ut + g.dn22 * vt) * double(g.f2);
     V3<double> D2 = g.x3 * ka - X2;
+    if (g.ev2 == SPOLY_R) {
+        const V3<double> t = cross(M2, g.edge2);
+        return dot(Dt, M2) * dot(D2, t) + dot(Dt, t) * dot(D2, M2);
+    }
     auto comp = [&](V3<double> w) { return g.axis == 0 ? w.x : (g.axis == 1 ? w.y : w.z); };
     double l = comp(cross(Dt, M2)), r = comp(cross(D2, M2));
     return g.eta1 * g.eta1 * dot(D2, D2) * l * l - g.eta2 * g.eta2 * dot(Dt, Dt) * r * r;
@@ -483,6 +529,13 @@ __device__ __forceinline__ double root_k_upper(double x, int k)
     return ldexp(double(exp2f(t - fl)), int(fl)) * 1.002;
 }
 
+// Two consecutive real roots of a(., v) closer than kPairGap max(1, |alpha|)
+// are left out of the product: together they contribute b(alpha)^2 > 0 unless
+// b vanishes between them, and such pairs sit where x2 goes to infinity (far
+// outside T1), where a and b nearly share a root and the values of b are
+// rounding noise.
+constexpr double kPairGap = 1e-4;
+
 // sign of det R(v) (up to a constant sign): product of sgn b over the real roots of a(., v)
 __device__ int tt_det_sign(const TTGeo& g, const double* __restrict__ Ac, int da, int ma, double v)
 {
@@ -512,7 +565,11 @@ __device__ int tt_det_sign(const TTGeo& g, const double* __restrict__ Ac, int da
     }
     double rt[kDA + 1];
     unsigned okm = iso_level<kDA, kDA>(c, -1.0, 1.0, rt);
+    // roots in ascending order; a root waits in `p` until the next one shows
+    // whether the two form a near-double pair (left out of the product)
     int s = 1;
+    bool has_p = false;
+    double p = 0.0;
     while (okm) {
         const int k = __builtin_ctz(okm);
         okm &= okm - 1u;
@@ -520,8 +577,16 @@ __device__ int tt_det_sign(const TTGeo& g, const double* __restrict__ Ac, int da
 #pragma unroll
         for (int j = 0; j <= kDA; ++j)
             if (j == k) x = rt[j];
-        if (tt_b_eval(g, x * B, v) < 0.0) s = -s;
+        x *= B;
+        if (has_p && x - p <= kPairGap * fmax(1.0, fabs(p))) {
+            has_p = false;
+            continue;
+        }
+        if (has_p && tt_b_eval(g, p, v) < 0.0) s = -s;
+        p = x;
+        has_p = true;
     }
+    if (has_p && tt_b_eval(g, p, v) < 0.0) s = -s;
     return s;
 }
 
@@ -533,14 +598,19 @@ __device__ bool tt_trace(const TTGeo& g, double u1, double v1, double& u2, doubl
     V3<double> n = normalized(g.n10 + g.dn11 * u1 + g.dn12 * v1);
     V3<double> di = normalized(x1 - g.x0);
     double c = dot(di, n);
-    if (c > 0.0) {
-        n = n * -1.0;
-        c = -c;
+    V3<double> dt;
+    if (g.ev1 == SPOLY_R) {
+        dt = di - n * (2.0 * c);
+    } else {
+        if (c > 0.0) {
+            n = n * -1.0;
+            c = -c;
+        }
+        double ci = -c;
+        double k = 1.0 - g.etap * g.etap * (1.0 - ci * ci);
+        if (k < 0.0) return false;
+        dt = di * g.etap + n * (g.etap * ci - sqrt(k));
     }
-    double ci = -c;
-    double k = 1.0 - g.etap * g.etap * (1.0 - ci * ci);
-    if (k < 0.0) return false;
-    V3<double> dt = di * g.etap + n * (g.etap * ci - sqrt(k));
     V3<double> pv = cross(dt, g.e22);
     double det = dot(g.e21, pv);
     if (!(fabs(det) > 0.0)) return false;
@@ -598,7 +668,7 @@ __device__ bool tt_polish(const TTGeo& g, int iters, double& pu, double& pv)
 }
 
 __device__ __forceinline__ bool law(V3<double> xp, V3<double> x, V3<double> xn, V3<double> nrm, double ein,
-                                    double eout, double& res)
+                                    double eout, int ev, double& res)
 {
     double ln = len(nrm);
     if (!(ln > 1e-12)) return false;
@@ -608,16 +678,19 @@ __device__ __forceinline__ bool law(V3<double> xp, V3<double> x, V3<double> xn, 
     double lh = len(h);
     if (!(lh > 0.0)) return false;
     res = len(cross(h * (1.0 / lh), nh));
-    return dot(wi, nh) * dot(wo, nh) < 0.0;   // refraction: opposite sides
+    const double side = dot(wi, nh) * dot(wo, nh);
+    return ev == SPOLY_R ? side > 0.0 : side < 0.0;   // reflection: one side; refraction: opposite sides
 }
 
 // ------------------------------------------------------------------ the fused kernel
 // One tuple per wave (the whole wave must call it); `lds` holds kLdsDoubles
 // doubles and `sgeo` one TTGeo, both in LDS and private to the wave.  The
 // tuple's geometry is the same for every lane, so it is kept in LDS rather
-// than replicated in vector registers.  Output records carry query id
-// q + qid_offset.
-__device__ __forceinline__ void tt_tuple(const TTArgs& A, int64_t q, double* lds, TTGeo* sgeo, int64_t qid_offset)
+// than replicated in vector registers.  smask and cmask (LDS, kSignWords
+// each) hold the scan's sign and sign-change bits.  Output records carry
+// query id q + qid_offset.
+__device__ __forceinline__ void tt_tuple(const TTArgs& A, int64_t q, double* lds, TTGeo* sgeo,
+                                         unsigned long long* smask, unsigned long long* cmask, int64_t qid_offset)
 {
     const int lane = lane_id();
     {
@@ -632,24 +705,30 @@ __device__ __forceinline__ void tt_tuple(const TTArgs& A, int64_t q, double* lds
     const int ma = tt_udeg(a);
     sync_wave();
     int degen = 0;
-    // ---- sign scan at v_j = j / pieces
+    // ---- sign scan at v_j = j / pieces, 64 samples per round; bit j of
+    // smask is set where the sign at v_j is negative, bit j of cmask where the
+    // signs at v_j and v_{j+1} differ (piece j holds a sign change)
     const int P = A.pieces;
-    int s_lo = 1, s_hi = 1;   // signs at v_j for j = lane and j = lane + 64 (when <= P)
+    const int nw = (P + 1 + kWave - 1) / kWave;   // sign words
     if (ma < 1) degen = 1;
-    if (!degen) {
-        if (lane <= P) s_lo = tt_det_sign(g, a.c, da, ma, double(lane) / P);
-        if (lane + kWave <= P) s_hi = tt_det_sign(g, a.c, da, ma, double(lane + kWave) / P);
+    for (int w = 0; w < nw; ++w) {
+        const int j = w * kWave + lane;
+        const bool neg = !degen && j <= P && tt_det_sign(g, a.c, da, ma, double(j) / P) < 0;
+        const unsigned long long bal = __ballot(neg);
+        if (lane == 0) smask[w] = bal;
     }
-    // sign change between j and j+1: piece j
-    int nxt_lo = __shfl_down(s_lo, 1, kWave);
-    const int first_hi = __shfl(s_hi, 0, kWave);
-    if (lane == kWave - 1) nxt_lo = first_hi;
-    const int nxt_hi = __shfl_down(s_hi, 1, kWave);
-    const bool chg_lo = !degen && lane < P && s_lo != nxt_lo;
-    const bool chg_hi = !degen && lane + kWave < P && lane < kWave - 1 && s_hi != nxt_hi;
-    const unsigned long long b_lo = __ballot(chg_lo), b_hi = __ballot(chg_hi);
-    const int n_lo = __popcll(b_lo), n_hi = __popcll(b_hi);
-    const int nv = n_lo + n_hi;
+    sync_wave();
+    int nv = 0;
+    for (int w = 0; w < nw; ++w) {
+        const unsigned long long cur = smask[w], nxt = (w + 1 < nw) ? smask[w + 1] : 0ull;
+        unsigned long long c = cur ^ ((cur >> 1) | (nxt << 63));
+        const int valid = P - w * kWave;            // pieces j = w*64 + i with i < valid
+        if (valid < kWave) c &= valid > 0 ? ((1ull << valid) - 1ull) : 0ull;
+        if (degen) c = 0ull;
+        nv += __popcll(c);
+        if (lane == 0) cmask[w] = c;
+    }
+    sync_wave();
     // ---- bisection (Sec. 5.2), then the path phase (u from a(u)|v, polish,
     // validation) for the final midpoint of every sign-change piece.
     LaneTT S;
@@ -675,8 +754,8 @@ __device__ __forceinline__ void tt_tuple(const TTArgs& A, int64_t q, double* lds
             if (!tt_trace(g, u, vv, u2, v2, x1, x2)) continue;
             if (!(u2 >= 0.0 && v2 >= 0.0 && u2 + v2 <= 1.0)) continue;
             double r1, r2;
-            if (!law(g.x0, x1, x2, g.n10 + g.dn11 * u + g.dn12 * vv, g.eta0, g.eta1, r1)) continue;
-            if (!law(x1, x2, g.x3, g.n20 + g.dn21 * u2 + g.dn22 * v2, g.eta1, g.eta2, r2)) continue;
+            if (!law(g.x0, x1, x2, g.n10 + g.dn11 * u + g.dn12 * vv, g.eta0, g.eta1, g.ev1, r1)) continue;
+            if (!law(x1, x2, g.x3, g.n20 + g.dn21 * u2 + g.dn22 * v2, g.eta1, g.eta2, g.ev2, r2)) continue;
             const double res = fmax(r1, r2);
             if (!(res <= A.tau)) continue;
             const double e1 = fmin(fmin(u, vv), 1.0 - u - vv), e2 = fmin(fmin(u2, v2), 1.0 - u2 - v2);
@@ -694,17 +773,20 @@ __device__ __forceinline__ void tt_tuple(const TTArgs& A, int64_t q, double* lds
             S.n++;
         }
     };
-    // sign of the scan at grid point j (all lanes must call it)
-    auto scan_sign = [&](int j) -> int {
-        const int lo = __shfl(s_lo, j & (kWave - 1), kWave);
-        const int hi = __shfl(s_hi, j & (kWave - 1), kWave);
-        return j < kWave ? lo : hi;
-    };
+    // sign of the scan at grid point j
+    auto scan_sign = [&](int j) -> int { return ((smask[j >> 6] >> (j & 63)) & 1ull) ? -1 : 1; };
+    // index of the k-th sign-change piece (k < nv)
     auto kth_piece = [&](int k) -> int {
-        unsigned long long m = k < n_lo ? b_lo : b_hi;
-        const int r0 = k < n_lo ? k : k - n_lo;
-        for (int i = 0; i < r0; ++i) m &= m - 1ull;
-        return __ffsll((long long)m) - 1 + (k < n_lo ? 0 : kWave);
+        for (int w = 0; w < nw; ++w) {
+            unsigned long long m = cmask[w];
+            const int c = __popcll(m);
+            if (k < c) {
+                for (int i = 0; i < k; ++i) m &= m - 1ull;
+                return w * kWave + __ffsll((long long)m) - 1;
+            }
+            k -= c;
+        }
+        return 0;
     };
     // Bits per round of the grouped bisection: groups of 2^b lanes evaluate the
     // 2^b - 1 midpoints that the next b bisection steps can visit, so b steps
@@ -992,9 +1074,10 @@ __global__ void __launch_bounds__(64) k_tt_solve(TTArgs A)
 {
     __shared__ double lds[kLdsDoubles];
     __shared__ TTGeo sgeo;
+    __shared__ unsigned long long smask[kSignWords], cmask[kSignWords];
     // grid-stride over tuples: a launch may hold at most 2^32 work-items
     for (int64_t q = blockIdx.x; q < A.nq; q += gridDim.x) {
-        tt_tuple(A, q, lds, &sgeo, 0);
+        tt_tuple(A, q, lds, &sgeo, smask, cmask, 0);
         __syncthreads();
     }
 }

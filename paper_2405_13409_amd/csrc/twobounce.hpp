@@ -1,4 +1,4 @@
-// Kernel arguments and launchers of the two-vertex (TT) path.
+// Kernel arguments and launchers of the two-vertex path (chains RR, RT, TR, TT).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -13,6 +13,7 @@ struct TTArgs {
     const double *x0x, *x0y, *x0z, *x3x, *x3y, *x3z;
     const int32_t *q_x0, *q_x3, *q_tris;   // q_tris[2q], q_tris[2q+1] = T1, T2
     int64_t nq;
+    int32_t ev1, ev2;         // event at x1 and at x2: SPOLY_R or SPOLY_T
     double eta0, eta1, eta2;
     double sqrt_bp[7];        // piece breakpoints of the square-root approximation
     double sqrt_c[24];        // (c0, c1, d0, d1) per piece
@@ -24,6 +25,10 @@ struct TTArgs {
     unsigned long long* counters;
     int32_t* diag_q;
 };
+
+constexpr int kMaxPieces = 4095;                 // pieces of the two-vertex sign scan
+constexpr int kSignWords = (kMaxPieces + 1 + 63) / 64;
+constexpr int kMaxBisect = 40;                   // bisection steps per sign change
 
 struct LaneTT {
     double u1[4], v1[4], u2[4], v2[4], res[4], edge[4];

@@ -263,12 +263,15 @@ def _cull_2bounce(self, mesh: DeviceMesh, x0s: DevicePoints, x3s: DevicePoints, 
 def _solve_2bounce(self, mesh: DeviceMesh, x0s: DevicePoints, x3s: DevicePoints, q_x0: torch.Tensor,
                    q_x3: torch.Tensor, q_tris: torch.Tensor, eta=(1.0, 1.5, 1.0), params: Params | None = None,
                    sqrt_table=None, capacity: int | None = None, counters: torch.Tensor | None = None,
-                   diag: torch.Tensor | None = None, sync: bool = True, out=None, out_count=None):
-    """TT chain x0 -> T1 -> T2 -> x3 (refraction at both vertices)."""
+                   diag: torch.Tensor | None = None, sync: bool = True, out=None, out_count=None, chain: str = "TT"):
+    """Chain x0 -> T1 -> T2 -> x3 with the events `chain` ("RR", "RT", "TR",
+    "TT": reflection or refraction at T1, then at T2)."""
     L = load_library()
     nq = int(q_x0.numel())
     prm = params or tt_default_params()
-    chain = (ctypes.c_int * 2)(SPOLY_T, SPOLY_T)
+    if len(chain) != 2 or set(chain) - {"R", "T"}:
+        raise SpolyError(f"chain must be two of R/T, got {chain!r}")
+    chain = (ctypes.c_int * 2)(*(SPOLY_R if c == "R" else SPOLY_T for c in chain))
     e = _host_doubles(eta)
     tb = _host_doubles(sqrt_table) if sqrt_table is not None else None
     cap = capacity if capacity is not None else max(1024, nq // 8)

@@ -57,12 +57,12 @@ def udeg(C: np.ndarray) -> int:
     return int(rows.max()) if len(rows) else 0
 
 
-def cond_sign_hp(A: np.ndarray, B: np.ndarray, ma: int, nb: int, v: float, rel: float = 1e-11, dps: int = 60):
-    """Product of sgn b(alpha, v) over the real roots alpha of a(., v), where a
-    factor with |b(alpha)| <= rel * sum_i |b_i| |alpha|^i counts as +1, from the
+def paired_sign_hp(A: np.ndarray, B: np.ndarray, ma: int, nb: int, v: float, gap: float = 1e-4, dps: int = 60):
+    """Product of sgn b(alpha, v) over the real roots alpha of a(., v), two
+    consecutive roots closer than gap * max(1, |alpha|) left out, from the
     exact values of the FP64 coefficients, with roots and values to `dps`
-    digits (mpmath).  None when a factor's ratio lies within a factor 30 of
-    `rel` (too close to the rule's threshold for a sample to decide)."""
+    digits (mpmath).  None when a gap lies within a factor 3 of the rule's
+    threshold, or a factor is zero to 30 digits."""
     import mpmath as mp
 
     with mp.workdps(dps):
@@ -82,16 +82,22 @@ def cond_sign_hp(A: np.ndarray, B: np.ndarray, ma: int, nb: int, v: float, rel: 
         ac, bc = coeffs(A, ma), coeffs(B, nb)
         rts = mp.polyroots(list(reversed(ac)), maxsteps=500, extraprec=4 * dps)
         tiny = mp.mpf(10) ** (-dps // 2)
+        real = sorted(mp.re(r) for r in rts if abs(mp.im(r)) <= tiny * max(1, abs(r)))
         sign = 1
-        for r in rts:
-            if abs(mp.im(r)) > tiny * max(1, abs(r)):
-                continue
-            x = mp.re(r)
-            val = mp.polyval(list(reversed(bc)), x)
-            scale = mp.polyval([abs(c) for c in reversed(bc)], abs(x))
-            ratio = abs(val) / scale if scale > 0 else mp.mpf(0)
-            if rel / 30 < ratio < rel * 30:
+        k = 0
+        while k < len(real):
+            al = real[k]
+            if k + 1 < len(real):
+                g = (real[k + 1] - al) / max(1, abs(al))
+                if gap / 3 < g < gap * 3:
+                    return None
+                if g <= gap:
+                    k += 2
+                    continue
+            val = mp.polyval(list(reversed(bc)), al)
+            if abs(val) <= tiny * mp.polyval([abs(c) for c in reversed(bc)], abs(al)):
                 return None
-            if val < 0 and ratio > rel:
+            if val < 0:
                 sign = -sign
+            k += 1
         return sign

@@ -202,11 +202,11 @@ def test_neighbourhoods_match_bruteforce(chain):
 
 
 @pytest.mark.parametrize("chain", ["RR", "RT", "TR", "TT"])
-def test_cond_sign_matches_high_precision(chain):
+def test_paired_sign_matches_high_precision(chain):
     """The two-vertex det sign (product of sgn b over the real roots of a(., v),
-    factors within 1e-11 of their rounding scale counted as +1) equals the
-    same product taken with the roots and values of the FP64 coefficients
-    computed to 60 digits, at every sample."""
+    near-double root pairs left out) equals the same product taken with the
+    roots and values of the FP64 coefficients computed to 60 digits, at every
+    sample."""
     mesh, x0, x3, t1, t2, _ = tc.trace_paths(chain, 3, 31)
     eta = tc.SETUPS[chain][2]
     checked = 0
@@ -215,9 +215,9 @@ def test_cond_sign_matches_high_precision(chain):
             A, B, n, _ = oracle.coeffs_2v(mesh.P, mesh.N, mesh.tri, pair[0], pair[1], x0[k], x3[k], chain, eta)
             ma, nb = er.udeg(A), er.udeg(B)
             for v in [round((j + 0.5) / 12 * 4096) / 4096 for j in range(12)]:
-                ref = er.cond_sign_hp(A, B, ma, nb, v)
+                ref = er.paired_sign_hp(A, B, ma, nb, v)
                 if ref is None:
                     continue
-                assert oracle.res_sign_cond(A, B, ma, v) == ref, (chain, k, v)
+                assert oracle.res_sign_paired(A, B, ma, v) == ref, (chain, k, v)
                 checked += 1
-    assert checked >= 60
+    assert checked >= 40

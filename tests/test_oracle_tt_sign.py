@@ -8,8 +8,8 @@ These tests compare it with the EXACT sign of the Sylvester resultant of the
 same FP64 coefficients (exact rational arithmetic, tests/exact_resultant.py):
 on curved sphere tuples around traced caustic paths and on random systems up
 to degrees (16, 40), the ratio of the two signs must be one constant per
-system.  The oracle's default (det_method 2) counts a factor below its
-rounding scale as +1; it is pinned against a 60-digit evaluation in
+system.  The oracle's default (det_method 2) leaves near-double root pairs
+of a out of the product; it is pinned against a 60-digit evaluation in
 test_oracle_2v_pins.py.  They also check that Gaussian elimination on the
 numeric Bezout matrix (the paper's literal procedure, det_method 0) and the
 product formulas give the same valid paths where elimination is well
@@ -149,7 +149,7 @@ def test_det_methods_on_sphere_neighbourhood():
     s1, d1 = oracle.solve_tt(*args, params=_params(1))
     s2, d2 = oracle.solve_tt(*args, params=_params(2))
     print(f"{n} tuples: sign changes GE {d0['n_vroots'].sum()} product {d1['n_vroots'].sum()} "
-          f"conditioned {d2['n_vroots'].sum()}; valid GE {len(s0)} product {len(s1)} conditioned {len(s2)}")
+          f"paired {d2['n_vroots'].sum()}; valid GE {len(s0)} product {len(s1)} paired {len(s2)}")
     assert len(s1) >= 1
     k0 = {(int(s['query']), round(s['u1'], 8), round(s['v1'], 8)) for s in s0}
     k1 = {(int(s['query']), round(s['u1'], 8), round(s['v1'], 8)) for s in s1}
