@@ -181,6 +181,34 @@ spoly_status spoly_solve_1bounce(spoly_ctx *ctx, const spoly_mesh *mesh,
                                  int32_t *diag_q, void *stream);
 
 /*
+ * spoly_solve_1bounce without any device allocation, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * and harnesses that forbid hipMalloc.  Same arguments, semantics and results
+ * as spoly_solve_1bounce, minus the context: the work runs on the device that
+ * is current, and the two-phase workspace is a file-scope device array of
+ * SPOLY_NOALLOC_SCRATCH_BYTES that every device the library runs on holds
+ * until the process ends (its device address is looked up on the first call
+ * on each device; no memory is allocated then either).  The workspace's
+ * counters are cleared by a kernel at the start of every call.
+ * Limits: n_queries <= SPOLY_NOALLOC_MAX_QUERIES_R (reflection) or
+ * SPOLY_NOALLOC_MAX_QUERIES_T (refraction); larger calls return
+ * SPOLY_E_CAPACITY and enqueue nothing.  Calls on one device share the one
+ * array: calls that overlap on one device (other streams, other threads) race
+ * and give undefined results; issue them on one stream.
+ */
+#define SPOLY_NOALLOC_SCRATCH_BYTES (64ll << 20)
+#define SPOLY_NOALLOC_MAX_QUERIES_R 2000000
+#define SPOLY_NOALLOC_MAX_QUERIES_T 450000
+spoly_status spoly_solve_1bounce_noalloc(const spoly_mesh *mesh,
+                                         const spoly_points *x0s, const spoly_points *x2s,
+                                         const int32_t *q_x0, const int32_t *q_x2, const int32_t *q_tri,
+                                         int64_t n_queries, spoly_event ev, double eta0, double eta1,
+                                         spoly_precision prec, const spoly_params *params,
+                                         spoly_solution *out, int64_t out_capacity,
+                                         unsigned long long *out_count, unsigned long long *counters,
+                                         int32_t *diag_q, void *stream);
+
+/*
  * Normal-cone cull for two specular vertices (chain x0 -> T1 -> T2 -> x3).
  * For every x0 in x0s, x3 in x3s and ordered pair of distinct triangles, keep
  * the tuple unless one vertex fails the half-vector / normal-cone test of

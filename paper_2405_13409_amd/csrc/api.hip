@@ -4,6 +4,7 @@
 
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 
 #include "../../include/spoly.h"
 #include "onebounce.hpp"
@@ -39,6 +40,13 @@ bool pts_ok(const spoly_points* p) { return p && p->x && p->y && p->z && p->n > 
 spoly_status dev_err(hipError_t e) { return e == hipSuccess ? SPOLY_OK : SPOLY_E_DEVICE; }
 
 }  // namespace
+
+static spoly_status ob_args(const spoly_mesh* mesh, const spoly_points* x0s, const spoly_points* x2s,
+                            const int32_t* q_x0, const int32_t* q_x2, const int32_t* q_tri, int64_t n_queries,
+                            spoly_event ev, double eta0, double eta1, spoly_precision prec,
+                            const spoly_params* params, spoly_solution* out, int64_t out_capacity,
+                            unsigned long long* out_count, unsigned long long* counters, int32_t* diag_q,
+                            spoly::OneBounceArgs& A);
 
 extern "C" {
 
@@ -120,18 +128,33 @@ static spoly_status grow(void** block, int64_t* cap, int64_t need, size_t per, s
     return SPOLY_OK;
 }
 
+// Item list of the two-phase one-vertex solve for `cap` candidates at p:
+// [256 B counters | items_v: kObEmit doubles | items_q, items_n, full_q: int32] per candidate
+constexpr size_t kObItemBytes = 8 * spoly::kObEmit + 12;
+constexpr size_t kObHeadBytes = 256;
+static void carve_ob_items(char* p, int64_t cap, spoly::OneBounceArgs& A)
+{
+    A.items_count = reinterpret_cast<unsigned long long*>(p);
+    A.items_v = reinterpret_cast<double*>(p + kObHeadBytes);
+    A.items_q = reinterpret_cast<int32_t*>(p + kObHeadBytes + size_t(cap) * 8 * spoly::kObEmit);
+    A.items_n = A.items_q + cap;
+    A.full_q = A.items_n + cap;
+    A.items_cap = cap;
+}
+// r(v) list of the refraction front for `cap` candidates at p:
+// [r(v): coef_bytes | iso_q, iso_st: int32] per candidate
+static void carve_ob_rlist(char* p, int64_t cap, size_t coef_bytes, spoly::OneBounceArgs& A)
+{
+    A.rlist = p;
+    A.iso_q = reinterpret_cast<int32_t*>(p + coef_bytes * size_t(cap));
+    A.iso_st = A.iso_q + cap;
+}
+
 static spoly_status ensure_ob_items(spoly_ctx* ctx, int64_t need, size_t coef_bytes, spoly::OneBounceArgs& A)
 {
-    // [256 B counters | items_v: kObEmit doubles | items_q, items_n, full_q: int32] per candidate
-    spoly_status st = grow(&ctx->ob_block, &ctx->ob_cap, need, 8 * spoly::kObEmit + 12, 256);
+    spoly_status st = grow(&ctx->ob_block, &ctx->ob_cap, need, kObItemBytes, kObHeadBytes);
     if (st != SPOLY_OK) return st;
-    char* p = static_cast<char*>(ctx->ob_block);
-    A.items_count = reinterpret_cast<unsigned long long*>(p);
-    A.items_v = reinterpret_cast<double*>(p + 256);
-    A.items_q = reinterpret_cast<int32_t*>(p + 256 + size_t(ctx->ob_cap) * 8 * spoly::kObEmit);
-    A.items_n = A.items_q + ctx->ob_cap;
-    A.full_q = A.items_n + ctx->ob_cap;
-    A.items_cap = ctx->ob_cap;
+    carve_ob_items(static_cast<char*>(ctx->ob_block), ctx->ob_cap, A);
     // [r(v) of listed candidates: coef_bytes | iso_q, iso_st: int32] per candidate, same capacity
     A.rlist = nullptr;
     A.iso_q = nullptr;
@@ -148,9 +171,7 @@ static spoly_status ensure_ob_items(spoly_ctx* ctx, int64_t need, size_t coef_by
         }
         ctx->ob_rbytes = per * ctx->ob_cap;
     }
-    A.rlist = ctx->ob_rblock;
-    A.iso_q = reinterpret_cast<int32_t*>(static_cast<char*>(ctx->ob_rblock) + size_t(coef_bytes) * ctx->ob_cap);
-    A.iso_st = A.iso_q + ctx->ob_cap;
+    carve_ob_rlist(static_cast<char*>(ctx->ob_rblock), ctx->ob_cap, coef_bytes, A);
     return SPOLY_OK;
 }
 
@@ -199,7 +220,32 @@ spoly_status spoly_solve_1bounce(spoly_ctx* ctx, const spoly_mesh* mesh, const s
                                  int64_t out_capacity, unsigned long long* out_count, unsigned long long* counters,
                                  int32_t* diag_q, void* stream)
 {
-    if (!ctx || !mesh_ok(mesh) || !pts_ok(x0s) || !pts_ok(x2s) || !params || !out_count) return SPOLY_E_INVALID_ARG;
+    if (!ctx) return SPOLY_E_INVALID_ARG;
+    spoly::OneBounceArgs A;
+    spoly_status st = ob_args(mesh, x0s, x2s, q_x0, q_x2, q_tri, n_queries, ev, eta0, eta1, prec, params, out,
+                              out_capacity, out_count, counters, diag_q, A);
+    if (st != SPOLY_OK) return st;
+    if (hipSetDevice(ctx->device) != hipSuccess) return SPOLY_E_DEVICE;
+    // the refraction front lists r(v) (13 doubles) of candidates between its two kernels
+    const size_t coef_bytes = ev == SPOLY_T ? 13 * 8 : 0;
+    st = ensure_ob_items(ctx, n_queries, coef_bytes, A);
+    if (st != SPOLY_OK) return st;
+    return dev_err(spoly::launch_onebounce_2phase(A, int(ev), int(prec), ctx->cus * 4,
+                                                  static_cast<hipStream_t>(stream)));
+}
+
+}  // extern "C"
+
+// Argument checks and kernel arguments shared by the one-vertex entry points
+// (the workspace pointers are filled by the caller).
+static spoly_status ob_args(const spoly_mesh* mesh, const spoly_points* x0s, const spoly_points* x2s,
+                            const int32_t* q_x0, const int32_t* q_x2, const int32_t* q_tri, int64_t n_queries,
+                            spoly_event ev, double eta0, double eta1, spoly_precision prec,
+                            const spoly_params* params, spoly_solution* out, int64_t out_capacity,
+                            unsigned long long* out_count, unsigned long long* counters, int32_t* diag_q,
+                            spoly::OneBounceArgs& A)
+{
+    if (!mesh_ok(mesh) || !pts_ok(x0s) || !pts_ok(x2s) || !params || !out_count) return SPOLY_E_INVALID_ARG;
     if (n_queries < 0 || out_capacity < 0 || (out_capacity > 0 && !out)) return SPOLY_E_INVALID_ARG;
     if (n_queries > 0 && (!q_x0 || !q_x2 || !q_tri)) return SPOLY_E_INVALID_ARG;
     if (ev != SPOLY_R && ev != SPOLY_T) return SPOLY_E_INVALID_ARG;
@@ -208,8 +254,6 @@ spoly_status spoly_solve_1bounce(spoly_ctx* ctx, const spoly_mesh* mesh, const s
     if (!(params->tau > 0.0) || !(params->iso_eps > 0.0) || params->polish_iters < 0 || !(params->u_margin >= 0.0) ||
         !(params->dedup >= 0.0))
         return SPOLY_E_INVALID_ARG;
-    if (hipSetDevice(ctx->device) != hipSuccess) return SPOLY_E_DEVICE;
-    spoly::OneBounceArgs A;
     A.px = mesh->px; A.py = mesh->py; A.pz = mesh->pz;
     A.nx = mesh->nx; A.ny = mesh->ny; A.nz = mesh->nz;
     A.tri = mesh->tri;
@@ -223,11 +267,83 @@ spoly_status spoly_solve_1bounce(spoly_ctx* ctx, const spoly_mesh* mesh, const s
     A.out = out; A.cap = out_capacity; A.out_count = out_count;
     A.counters = counters; A.diag_q = diag_q;
     A.refine_v = (ev == SPOLY_R && prec == SPOLY_FP32_POLISH64) ? 1 : 0;
-    // the refraction front lists r(v) (13 doubles) of candidates between its two kernels
-    const size_t coef_bytes = ev == SPOLY_T ? 13 * 8 : 0;
-    const spoly_status st = ensure_ob_items(ctx, n_queries, coef_bytes, A);
+    return SPOLY_OK;
+}
+
+// ---------------------------------------------------------------- no-allocation variant
+// The two-phase workspace of spoly_solve_1bounce_noalloc lives in this
+// file-scope device array; each device holds its own copy until the process
+// ends.  Host code never uses the array's name as an address: its device
+// address is looked up per device (hipGetSymbolAddress, with that device
+// current) on the first call on that device and kept in g_scratch.
+static __device__ __align__(256) unsigned char scratch[SPOLY_NOALLOC_SCRATCH_BYTES];
+static_assert(kObHeadBytes + kObItemBytes * size_t(SPOLY_NOALLOC_MAX_QUERIES_R) <= SPOLY_NOALLOC_SCRATCH_BYTES,
+              "reflection workspace exceeds the scratch array");
+static_assert((kObHeadBytes + kObItemBytes * size_t(SPOLY_NOALLOC_MAX_QUERIES_T) + 255) / 256 * 256 +
+                      (13 * 8 + 8) * size_t(SPOLY_NOALLOC_MAX_QUERIES_T) <= SPOLY_NOALLOC_SCRATCH_BYTES,
+              "refraction workspace exceeds the scratch array");
+
+namespace {
+constexpr int kMaxDevices = 64;
+struct ScratchSlot {
+    void* ptr;
+    int cus;
+};
+ScratchSlot g_scratch[kMaxDevices];
+std::mutex g_scratch_mu;
+
+spoly_status scratch_for_current_device(ScratchSlot& slot)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return SPOLY_E_DEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    ScratchSlot& s = g_scratch[dev];
+    if (!s.ptr) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return SPOLY_E_DEVICE;
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+        s.cus = cus;
+        s.ptr = p;
+    }
+    slot = s;
+    return SPOLY_OK;
+}
+}  // namespace
+
+extern "C" {
+
+spoly_status spoly_solve_1bounce_noalloc(const spoly_mesh* mesh, const spoly_points* x0s, const spoly_points* x2s,
+                                         const int32_t* q_x0, const int32_t* q_x2, const int32_t* q_tri,
+                                         int64_t n_queries, spoly_event ev, double eta0, double eta1,
+                                         spoly_precision prec, const spoly_params* params, spoly_solution* out,
+                                         int64_t out_capacity, unsigned long long* out_count,
+                                         unsigned long long* counters, int32_t* diag_q, void* stream)
+{
+    spoly::OneBounceArgs A;
+    spoly_status st = ob_args(mesh, x0s, x2s, q_x0, q_x2, q_tri, n_queries, ev, eta0, eta1, prec, params, out,
+                              out_capacity, out_count, counters, diag_q, A);
     if (st != SPOLY_OK) return st;
-    return dev_err(spoly::launch_onebounce_2phase(A, int(ev), int(prec), ctx->cus * 4,
+    const int64_t max_q = ev == SPOLY_T ? SPOLY_NOALLOC_MAX_QUERIES_T : SPOLY_NOALLOC_MAX_QUERIES_R;
+    if (n_queries > max_q) return SPOLY_E_CAPACITY;
+    ScratchSlot slot;
+    st = scratch_for_current_device(slot);
+    if (st != SPOLY_OK) return st;
+    // [items for max_q candidates | refraction r(v) list for max_q candidates]; the layout uses the
+    // largest query count of the event, so its size does not depend on n_queries
+    const size_t coef_bytes = ev == SPOLY_T ? 13 * 8 : 0;
+    char* base = static_cast<char*>(slot.ptr);
+    carve_ob_items(base, max_q, A);
+    A.rlist = nullptr;
+    A.iso_q = nullptr;
+    A.iso_st = nullptr;
+    if (coef_bytes) {
+        const size_t items = kObHeadBytes + kObItemBytes * size_t(max_q);
+        const size_t off = (items + 255) / 256 * 256;
+        carve_ob_rlist(base + off, max_q, coef_bytes, A);
+    }
+    return dev_err(spoly::launch_onebounce_2phase(A, int(ev), int(prec), slot.cus * 4,
                                                   static_cast<hipStream_t>(stream)));
 }
 

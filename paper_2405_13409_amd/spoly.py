@@ -27,7 +27,7 @@ assert SOLUTION_DTYPE.itemsize == 56
 EXPORTED = ("spoly_ctx_create", "spoly_ctx_destroy", "spoly_default_params", "spoly_status_str",
             "spoly_cull_1bounce", "spoly_solve_1bounce", "spoly_cull_2bounce", "spoly_solve_nbounce",
             "spoly_prune_score", "spoly_pruner_fwd_bwd", "spoly_pruner_step", "spoly_pruner_features",
-            "spoly_solve_mixed", "spoly_tt_default_params")
+            "spoly_solve_mixed", "spoly_tt_default_params", "spoly_solve_1bounce_noalloc")
 PRUNER_NPARAMS = 38657
 
 
@@ -84,6 +84,10 @@ def load_library(path: str = LIB_PATH):
     L.spoly_solve_1bounce.argtypes = [P, ctypes.POINTER(Mesh), ctypes.POINTER(Points), ctypes.POINTER(Points), P, P, P,
                                       I64, ctypes.c_int, D, D, ctypes.c_int, ctypes.POINTER(Params), P, I64, P, P, P, P]
     L.spoly_solve_1bounce.restype = ctypes.c_int
+    L.spoly_solve_1bounce_noalloc.argtypes = [ctypes.POINTER(Mesh), ctypes.POINTER(Points), ctypes.POINTER(Points),
+                                              P, P, P, I64, ctypes.c_int, D, D, ctypes.c_int, ctypes.POINTER(Params),
+                                              P, I64, P, P, P, P]
+    L.spoly_solve_1bounce_noalloc.restype = ctypes.c_int
     L.spoly_cull_2bounce.argtypes = [P, ctypes.POINTER(Mesh), ctypes.POINTER(Points), ctypes.POINTER(Points), P, D,
                                      P, P, P, P, I64, P, P]
     L.spoly_cull_2bounce.restype = ctypes.c_int

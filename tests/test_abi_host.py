@@ -72,3 +72,28 @@ def test_ctx_create_without_device_reports_device_error():
     L = _lib()
     h = ctypes.c_void_p()
     assert L.spoly_ctx_create(ctypes.byref(h), 0) == spoly.SPOLY_E_DEVICE
+
+
+def test_noalloc_rejects_oversize_and_bad_args_on_host():
+    """The no-allocation one-vertex entry point checks its arguments and its
+    workspace limit before touching the device."""
+    from paper_2405_13409_amd import spoly
+
+    L = _lib()
+    p = spoly.default_params()
+    cnt = ctypes.c_ulonglong(0)
+    st = L.spoly_solve_1bounce_noalloc(None, None, None, None, None, None, 0, 0, 1.0, 1.0, 0, ctypes.byref(p),
+                                       None, 0, ctypes.byref(cnt), None, None, None)
+    assert st == spoly.SPOLY_E_INVALID_ARG
+    # well-formed (never dereferenced) pointers, one query over each limit
+    dummy = (ctypes.c_double * 4)()
+    ids = (ctypes.c_int32 * 4)()
+    addr = ctypes.cast(dummy, ctypes.c_void_p).value
+    mesh = spoly.Mesh(addr, addr, addr, addr, addr, addr, ctypes.cast(ids, ctypes.c_void_p).value, 3, 1)
+    pts = spoly.Points(addr, addr, addr, 1)
+    q = ctypes.cast(ids, ctypes.c_void_p)
+    for ev, lim in ((spoly.SPOLY_R, 2000000), (spoly.SPOLY_T, 450000)):
+        st = L.spoly_solve_1bounce_noalloc(ctypes.byref(mesh), ctypes.byref(pts), ctypes.byref(pts), q, q, q,
+                                           lim + 1, ev, 1.0, 1.0, 0, ctypes.byref(p), None, 0, ctypes.byref(cnt),
+                                           None, None, None)
+        assert st == spoly.SPOLY_E_CAPACITY
