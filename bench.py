@@ -23,19 +23,35 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+METRIC = "candidate solves/s & valid paths/s, pruned vs exhaustive at recall>=99.9%"
 
+PEAK_FP32 = 157.3   # TFLOP/s, published FP32 vector peak (packed FP32 instructions)
 PEAK_VALU = 78.6    # TFLOP/s: 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, fp32 (non-packed) and fp64
+PEAK_BF16 = 2500.0  # TFLOP/s, dense bf16 matrix cores
 PEAK_HBM = 8000.0   # GB/s
+VALU_ISSUE = 256 * 4 * 2.4e9 / 4   # wave64 VALU instructions per second (16-lane SIMDs, 4 per CU)
 
-# HBM bytes of one reflection solve (k_ob_front<float,R> + k_ob_back<R> + k_ob_full<R>) on the glints
-# workload, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch), scaled by what the same
-# counters read for a plain 256 MiB device copy (FETCH x2.0, WRITE x1.0).  Valid only for the kernel
-# sources they were taken on (sha256 prefix over the files in _KERNEL_SOURCES, the cull included: it sets
-# the order of the candidates); otherwise traffic is null.
-TRAFFIC_R = {"sha": "2e33cac3b84d0211", "candidates": 99118956,
-             "fetch_kib": 680274.5 + 658461.1 + 34517.1, "write_kib": 1897214.1 + 491000.9 + 41.8,
-             "fetch_scale": 262144.0 / 131084.5, "write_scale": 262144.0 / 262144.0}
-_KERNEL_SOURCES = ("onebounce.hip", "spoly_dev.hpp", "laplace_gen.inc", "onebounce.hpp", "cull.hip")
+# Algorithmic operations per instance by stage (coefficients, elimination, root finding in v, path phase),
+# from the oracle's op counter over seeded samples of each workload: profiles/algorithmic_flops.md, written
+# by `python oracle/opcount.py`.
+OPS = {
+    "glints_R": (783, 1264, 440, 71),
+    "glints_T": (1439, 7075, 894, 102),
+    "caustic_TT": (368162, 1154952, 1316046, 7323),
+    "mirror_RR": (17860, 874785, 38675, 650),
+}
+PRUNER_FLOP = 2 * (42 * 128 + 2 * 128 * 128 + 128)   # multiply-adds of the four dense layers, per tuple
+
+# HBM bytes of the reflection front kernel k_ob_front<float,R> on the glints workload, from rocprofv3 --pmc
+# FETCH_SIZE and WRITE_SIZE (KiB per dispatch), scaled by what the same counters read for a plain 256 MiB
+# device copy.  Valid only for the kernel sources they were taken on (sha256 prefix over _KERNEL_SOURCES,
+# the cull included: it sets the order of the candidates); otherwise traffic is null.
+TRAFFIC_FRONT = None
+# VALU wave-instructions per launch (rocprofv3 --pmc SQ_INSTS_VALU) of each kernel on its workload, under the
+# same source check.
+VALU_INSTS = None
+_KERNEL_SOURCES = ("onebounce.hip", "spoly_dev.hpp", "laplace_gen.inc", "onebounce.hpp", "cull.hip",
+                   "twobounce.hip", "twobounce.hpp", "pruner.hip")
 
 
 def _kernel_sha() -> str:
@@ -49,89 +65,31 @@ def _kernel_sha() -> str:
 
 
 def traffic_bytes(candidates: int):
-    """HBM bytes per reflection-solve launch for `candidates` instances, or None
-    if the kernels changed since the counters were taken."""
-    t = TRAFFIC_R
-    if _kernel_sha() != t["sha"]:
+    """HBM bytes per front launch for `candidates` instances, or None if the
+    kernels changed since the counters were taken."""
+    t = TRAFFIC_FRONT
+    if t is None or _kernel_sha() != t["sha"]:
         return None
     per = (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024.0 / t["candidates"]
     return per * candidates
-PEAK_VALU_PACKED_FP32 = 157.3
-METRIC = "candidate solves/s & valid paths/s, pruned vs exhaustive at recall>=99.9%"
 
 
-# ------------------------------------------------------------------ algorithmic flop model
-class _P:
-    """Degree-tracking stand-in of a bivariate polynomial; counts the flops of
-    the coefficient-phase arithmetic exactly as the kernel performs it."""
-    flops = 0
-
-    def __init__(self, d):
-        self.d = d
-
-    @staticmethod
-    def ts(d):
-        return (d + 1) * (d + 2) // 2
-
-    def __mul__(self, o):
-        _P.flops += 2 * _P.ts(self.d) * _P.ts(o.d)
-        return _P(self.d + o.d)
-
-    def __add__(self, o):
-        d = max(self.d, o.d)
-        _P.flops += 3 * _P.ts(d)
-        return _P(d)
-
-    __sub__ = __add__
+def valu_insts(kernel: str):
+    t = VALU_INSTS
+    if t is None or _kernel_sha() != t["sha"] or kernel not in t:
+        return None
+    return t[kernel]
 
 
-def _vdot(a, b):
-    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]
-
-
-def _vcross(a, b):
-    return [a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]]
-
-
-def coefficient_flops(ev: str) -> int:
-    _P.flops = 0
-    x1 = [_P(1)] * 3
-    n = [_P(1)] * 3
-    c = [_P(0)] * 3
-    d0 = [x1[k] - c[k] for k in range(3)]
-    d1 = [c[k] - x1[k] for k in range(3)]
-    _vdot(_vcross(d0, c), n)
-    if ev == "R":
-        t = _vcross(n, c)
-        _vdot(d0, n) * _vdot(d1, t) + _vdot(d0, t) * _vdot(d1, n)
-    else:
-        l, r = _vcross(d0, n)[0], _vcross(d1, n)[0]
-        (_vdot(d1, d1) * (l * l)) + (_vdot(d0, d0) * (r * r))
-    return _P.flops
-
-
-def elimination_flops(ev: str) -> int:
-    """2 x (fma + mul) count of the generated Bezout + Laplace code."""
-    name = "r_interp" if ev == "R" else "t_interp"
-    path = os.path.join(ROOT, "paper_2405_13409_amd", "csrc", "laplace_gen.inc")
-    txt = open(path).read()
-    body = txt.split(f"elim_{name}(")[1].split("\n}\n")[0]
-    return 2 * (body.count("fma(") + body.count(" * "))
-
-
-def isolation_fixed_flops(ev: str) -> int:
-    """Derivative chain plus the sign evaluations at every piece end (the
-    data-independent part of the recursive isolation of Sec. 5.2)."""
-    D = 9 if ev == "R" else 12
-    f = 0
-    for d in range(1, D + 1):
-        f += d                 # derivative coefficients
-        f += (d + 1) * 2 * d   # Horner at d+1 piece ends (upper bound: all breakpoints present)
-    return f
-
-
-def per_instance_flops(ev: str) -> int:
-    return coefficient_flops(ev) + elimination_flops(ev) + isolation_fixed_flops(ev)
+def kernel_obj(name, flop, ms, peak, dtype, insts=None, **extra):
+    """Roofline object of one kernel: algorithmic flops per launch / its duration."""
+    ach = flop / (ms * 1e-3) / 1e12
+    o = {"kernel": name, "dtype": dtype, "bound": "alu", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+         "frac": ach / peak, "ms": ms, "algorithmic_flop": flop}
+    if insts is not None:
+        o["valu_issue_frac"] = insts / (ms * 1e-3) / VALU_ISSUE
+    o.update(extra)
+    return o
 
 
 # ------------------------------------------------------------------ bench
@@ -144,8 +102,9 @@ def main():
     ap.add_argument("--res", type=int, default=256, help="shading points per side")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
-    ap.add_argument("--legs", default="glints,mixed,caustic",
-                    help="comma list: glints (the headline line), mixed (2M-instance persistent launch), "
+    ap.add_argument("--legs", default="glints,rr,mixed,caustic",
+                    help="comma list: glints (the headline line), rr (two reflections between two wavy mirrors), "
+                         "mixed (2M-instance persistent launch), "
                          "caustic (learned pruner against the exhaustive two-vertex solve)")
     ap.add_argument("--mixed-total", type=int, default=2_000_000)
     ap.add_argument("--caustic-stride", type=int, default=1, help="every k-th receiver of the 64x64 grid")
@@ -168,12 +127,13 @@ def main():
 
     spoly.load_library()
     prec = spoly.SPOLY_FP32_POLISH64 if args.precision == "fp32" else spoly.SPOLY_FP64
-    ctx = spoly.Context(0)
     mesh = scenes.glints_large_mesh()
     light = scenes.GLINTS_LARGE_LIGHT
+    events = [("R", 1.0, 1.0), ("T", 1.5, 1.0)]
+    # one context per event, so that each keeps the kernel timings of its own solve
+    ctxs = {ev: spoly.Context(0) for ev, _, _ in events}
     dm = spoly.DeviceMesh(mesh.P, mesh.N, mesh.tri)
     dl = spoly.DevicePoints(light)
-    events = [("R", 1.0, 1.0), ("T", 1.5, 1.0)]
     pts = {ev: spoly.DevicePoints(scenes.glints_large_points(ev, args.res)) for ev, _, _ in events}
     L = spoly.load_library()
     import ctypes
@@ -181,9 +141,9 @@ def main():
     # buffers sized from one untimed pass
     cap_c, cap_s = {}, {}
     for ev, e0, e1 in events:
-        q0, q2, qt = ctx.cull_1bounce(dm, pts[ev], dl, e0, e1, 1e-3)
+        q0, q2, qt = ctxs[ev].cull_1bounce(dm, pts[ev], dl, e0, e1, 1e-3)
         cap_c[ev] = int(q0.numel() * 1.05) + 1024
-        sols = ctx.solve_1bounce(dm, pts[ev], dl, q0, q2, qt, ev, e0, e1, prec)
+        sols = ctxs[ev].solve_1bounce(dm, pts[ev], dl, q0, q2, qt, ev, e0, e1, prec)
         cap_s[ev] = int(len(sols) * 1.2) + 1024
         del q0, q2, qt
     buf = {}
@@ -195,18 +155,22 @@ def main():
                        out=torch.empty(cap_s[ev] * spoly.SOLUTION_DTYPE.itemsize, dtype=torch.uint8, device="cuda"),
                        scount=torch.zeros(1, dtype=torch.int64, device="cuda"))
     prm = spoly.default_params()
+    prm.flags = spoly.SPOLY_FLAG_STAGE_TIMES
     stream = torch.cuda.current_stream()
     sptr = ctypes.c_void_p(stream.cuda_stream)
     p = lambda t: ctypes.c_void_p(t.data_ptr())  # noqa: E731
     solve_ms = {ev: [] for ev, _, _ in events}
+    stage_ms = {ev: [] for ev, _, _ in events}
+    n_cand = {}
 
     def step(record: bool):
         tot_inst, tot_sol = 0, 0
         for ev, e0, e1 in events:
             b = buf[ev]
+            h = ctxs[ev].h
             b["ccount"].zero_()
             b["scount"].zero_()
-            st = L.spoly_cull_1bounce(ctx.h, ctypes.byref(dm.c), ctypes.byref(pts[ev].c), ctypes.byref(dl.c), e0, e1,
+            st = L.spoly_cull_1bounce(h, ctypes.byref(dm.c), ctypes.byref(pts[ev].c), ctypes.byref(dl.c), e0, e1,
                                       1e-3, p(b["q0"]), p(b["q2"]), p(b["qt"]), cap_c[ev], p(b["ccount"]), sptr)
             assert st == 0
             nq = int(b["ccount"].item())
@@ -214,19 +178,22 @@ def main():
             e_a = torch.cuda.Event(enable_timing=True)
             e_b = torch.cuda.Event(enable_timing=True)
             e_a.record(stream)
-            st = L.spoly_solve_1bounce(ctx.h, ctypes.byref(dm.c), ctypes.byref(pts[ev].c), ctypes.byref(dl.c),
+            st = L.spoly_solve_1bounce(h, ctypes.byref(dm.c), ctypes.byref(pts[ev].c), ctypes.byref(dl.c),
                                        p(b["q0"]), p(b["q2"]), p(b["qt"]), nq, 1 if ev == "T" else 0, e0, e1, prec,
                                        ctypes.byref(prm), p(b["out"]), cap_s[ev], p(b["scount"]), None, None, sptr)
             assert st == 0
             e_b.record(stream)
             if record:
-                solve_ms[ev].append((e_a, e_b, nq))
+                solve_ms[ev].append((e_a, e_b))
+            n_cand[ev] = nq
             tot_inst += nq
         torch.cuda.synchronize()
         for ev, _, _ in events:
             ns = int(buf[ev]["scount"].item())
             assert ns <= cap_s[ev]
             tot_sol += ns
+            if record:
+                stage_ms[ev].append(ctxs[ev].stage_times())
         return tot_inst, tot_sol
 
     for _ in range(args.warmup):
@@ -243,14 +210,44 @@ def main():
     dt = time.perf_counter() - t0
     ms_step = dt / args.steps * 1e3
 
-    # dominant kernel: the reflection solve (front + back + full-list kernels of one spoly_solve_1bounce call)
-    rec = solve_ms["R"]
-    avg_ms = float(np.mean([a.elapsed_time(b) for a, b, _ in rec]))
-    n_r = rec[0][2]
-    fl = per_instance_flops("R") * n_r
-    achieved = fl / (avg_ms * 1e-3) / 1e12
-    t_rec = solve_ms["T"]
-    avg_ms_t = float(np.mean([a.elapsed_time(b) for a, b, _ in t_rec]))
+    # per-kernel times (HIP events recorded around each kernel on the launch stream)
+    st_r = np.mean(np.array(stage_ms["R"]), axis=0)   # front, back, full list
+    st_t = np.mean(np.array(stage_ms["T"]), axis=0)   # coefficients, isolation, back, full list
+    call_r = float(np.mean([a.elapsed_time(b) for a, b in solve_ms["R"]]))
+    call_t = float(np.mean([a.elapsed_time(b) for a, b in solve_ms["T"]]))
+    nr, nt_ = n_cand["R"], n_cand["T"]
+    oR, oT = OPS["glints_R"], OPS["glints_T"]
+    fp = "f32" if args.precision == "fp32" else "f64"
+    front = kernel_obj("k_ob_front<float,R>" if fp == "f32" else "k_ob_front<double,R>",
+                       (oR[0] + oR[1] + oR[2]) * nr, float(st_r[0]), PEAK_FP32 if fp == "f32" else PEAK_VALU, fp,
+                       valu_insts("k_ob_front_R"),
+                       traffic=traffic_bytes(nr), instances=nr,
+                       flop_per_instance=oR[0] + oR[1] + oR[2],
+                       peak_nonpacked=PEAK_VALU,
+                       frac_nonpacked=(oR[0] + oR[1] + oR[2]) * nr / (float(st_r[0]) * 1e-3) / 1e12 / PEAK_VALU,
+                       peak_note="FP32 peak counts packed-FP32 FMAs, which this build does not emit; "
+                                 "frac_nonpacked is against the 78.6 TFLOP/s non-packed vector rate")
+    kernels = [
+        front,
+        kernel_obj("k_ob_back<R>", oR[3] * nr, float(st_r[1]), PEAK_VALU, "f64", valu_insts("k_ob_back_R"),
+                   note="path phase of the candidates with roots (u solve, FP64 polish, validation)"),
+        kernel_obj("k_ob_full<R>", oR[3] * nr, float(st_r[2]), PEAK_VALU, "f64", valu_insts("k_ob_full_R"),
+                   note="FP64 re-solve of the handed-off candidates; flops counted as the path phase only"),
+        kernel_obj("k_ob_coef<double,T>", (oT[0] + oT[1]) * nt_, float(st_t[0]), PEAK_VALU, "f64",
+                   valu_insts("k_ob_coef_T")),
+        kernel_obj("k_ob_iso<double,T>", oT[2] * nt_, float(st_t[1]), PEAK_VALU, "f64", valu_insts("k_ob_iso_T")),
+        kernel_obj("k_ob_back<T>", oT[3] * nt_, float(st_t[2]), PEAK_VALU, "f64", valu_insts("k_ob_back_T")),
+    ]
+    hbm = traffic_bytes(nr)
+    roofline = {"bound": "alu", "kernel": front["kernel"], "achieved": front["achieved"], "peak": front["peak"],
+                "unit": "TFLOP/s", "frac": front["frac"], "traffic": hbm,
+                "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                "hbm_GBps": (hbm / (float(st_r[0]) * 1e-3) / 1e9) if hbm else None,
+                "flop_per_instance": front["flop_per_instance"], "instances": nr, "ms": front["ms"],
+                "peak_nonpacked": PEAK_VALU, "frac_nonpacked": front["frac_nonpacked"],
+                "valu_issue_frac": front.get("valu_issue_frac"),
+                "flop_source": "oracle op counter (profiles/algorithmic_flops.md): coefficients + elimination + "
+                               "isolation of a reflection candidate"}
 
     out = {
         "metric": METRIC,
@@ -263,7 +260,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "dtype": fp,
         "data": "synthetic",
         "config": {
             "workload": f"glints: 128x128 heightfield (32768 tris), {args.res}x{args.res} points at z=+2 (R) and "
@@ -273,27 +270,22 @@ def main():
             "valid_paths_per_step": sols // args.steps,
         },
         "valid_paths_per_s": sols / dt,
-        "stage_ms": {"solve_R": avg_ms, "solve_T": avg_ms_t},
-        "roofline": {
-            "bound": "alu",
-            "kernel": "reflection solve: k_ob_front<float,R> + k_ob_back<R> + k_ob_full<R>",
-            "achieved": achieved,
-            "peak": PEAK_VALU,
-            "unit": "TFLOP/s",
-            "frac": achieved / PEAK_VALU,
-            "traffic": traffic_bytes(n_r),
-            "traffic_unit": "bytes per launch (HBM, FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-            "hbm_GBps": (traffic_bytes(n_r) / (avg_ms * 1e-3) / 1e9) if traffic_bytes(n_r) else None,
-            "flops_per_instance": per_instance_flops("R"),
-            "peak_note": "fp32/fp64 vector FMA without packed fp32 (packed-fp32 peak 157.3)",
-        },
+        "stage_ms": {"solve_R": call_r, "solve_T": call_t, "kernels_R": [float(x) for x in st_r],
+                     "kernels_T": [float(x) for x in st_t]},
+        "roofline": roofline,
+        "kernels": kernels,
     }
+    for ev in ctxs:
+        ctxs[ev].close()
+    ctx = spoly.Context(0)
+    if "rr" in legs:
+        out["two_reflections"] = rr_leg(args, ctx)
     if "mixed" in legs:
         out["mixed"] = mixed_leg(args, ctx)
     if "caustic" in legs:
         out["pruned_vs_exhaustive"] = caustic_leg(args, ctx)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args, mesh, light)
+        out["cpu_baseline"] = cpu_baseline(args, mesh, light, ctx)
     print(json.dumps(out), flush=True)
     ctx.close()
 
@@ -378,6 +370,48 @@ def mixed_leg(args, ctx):
             "autotune_ms": timings, "graph": True, "precision": "fp32 bulk, fp64 polish (TT fp64)"}
 
 
+def rr_leg(args, ctx):
+    """Two reflections (RR, Sec. 4.5) between two wavy mirrors facing each other
+    across a gap: every cone-culled (receiver, T1, T2, light) tuple of a 24x24
+    receiver grid in the gap, solved in one launch (FP64, 100 pieces x 10
+    bisection steps)."""
+    import torch
+    from paper_2405_13409_amd import scenes, spoly
+
+    mesh = scenes.mirror_gap()
+    rec = scenes.points_grid(24, -0.9, 0.9, 0.5)
+    dm = spoly.DeviceMesh(mesh.P, mesh.N, mesh.tri)
+    d0, dl = spoly.DevicePoints(rec), spoly.DevicePoints(scenes.MIRROR_GAP_LIGHT)
+    eta = (1.0, 1.0, 1.0)
+    q0, q3, qt = ctx.cull_2bounce(dm, d0, dl, eta, 1e-3)
+    n = int(q0.numel())
+    first = ctx.solve_2bounce(dm, d0, dl, q0, q3, qt, eta, chain="RR")
+    cap = len(first) + 4096
+    out = torch.empty(cap * spoly.SOLUTION_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    ms = []
+    for _ in range(3):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        ctx.solve_2bounce(dm, d0, dl, q0, q3, qt, eta, chain="RR", out=out, out_count=cnt, sync=False)
+        b.record()
+        b.synchronize()
+        ms.append(a.elapsed_time(b))
+    paths = int(cnt.item())
+    med = float(np.median(ms))
+    ops = OPS["mirror_RR"]
+    return {"workload": f"{len(rec)} receivers (24x24 grid on [-0.9,0.9]^2 at z=0.5) between two 16x16 wavy "
+                        f"heightfields (1024 tris) facing each other across a gap of 1, light (0.15,-0.1,0.5); "
+                        f"RR chain, {n} cone-culled tuples",
+            "tuples": n, "ms": med, "tuples_per_s": n / med * 1e3, "valid_paths": paths,
+            "valid_paths_per_s": paths / med * 1e3, "us_per_tuple": med * 1e3 / n,
+            "paper_context": "Table 3, RR (bisection solver, RTX 4080, its own two-dragon scene): 4.936 us per "
+                             "triangle pair",
+            "roofline": kernel_obj("k_tt_solve (RR)", sum(ops) * n, med, PEAK_VALU, "f64", valu_insts("k_tt_solve_RR"),
+                                   flop_per_instance=sum(ops))}
+
+
 def caustic_leg(args, ctx):
     """Learned pruner against the exhaustive two-vertex solve on a subset of
     the 64x64 receiver grid (every --caustic-stride-th receiver)."""
@@ -402,41 +436,112 @@ def caustic_leg(args, ctx):
                      f"icosphere 1280 tris IOR 1.5, light (0.1,0.05,1.5); TT chain")
     r["threshold"] = net.threshold
     r["train"] = train_pruner.load_meta(path)
+    ops = OPS["caustic_TT"]
+    r["kernels"] = [
+        kernel_obj("k_tt_solve (TT, exhaustive)", sum(ops) * r["n_tuples"], r["ms_exhaustive"], PEAK_VALU, "f64",
+                   valu_insts("k_tt_solve_TT"), flop_per_instance=sum(ops)),
+        dict(kernel_obj("pruner scoring (feature gather + 4 dense layers)", PRUNER_FLOP * r["n_tuples"],
+                        r["ms_score"], PEAK_BF16, "bf16"), bound="mfma", flop_per_instance=PRUNER_FLOP),
+    ]
     return r
 
 
-def cpu_baseline(args, mesh, light):
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _errors_vs_oracle(gpu, orc, diag, nq, tau=1e-6, band=1e-4):
+    """Per-result error of the GPU solutions against the FP64 oracle's on the
+    same candidates: queries whose solution count differs (ambiguous ones
+    excluded: a root pair or tangency below the FP32 path's resolution, a
+    solution in the edge band or with a residual near tau), and max / p99 of
+    |du|, |dv| over the matched solutions."""
+    amb = (diag["tangency"] < 1e-5) | (diag["min_gap"] < 1e-4)
+    amb[orc["query"][(orc["edge"] < band) | ((orc["residual"] > tau / 10) & (orc["residual"] < 10 * tau))]] = True
+    amb[gpu["query"][(gpu["edge"] < band) | ((gpu["residual"] > tau / 10) & (gpu["residual"] < 10 * tau))]] = True
+    g = gpu[~amb[gpu["query"]]]
+    o = orc[~amb[orc["query"]]]
+    g = g[np.lexsort((g["u"][:, 0], g["v"][:, 0], g["query"]))]
+    o = o[np.lexsort((o["u1"], o["v1"], o["query"]))]
+    gq, oq = np.bincount(g["query"], minlength=nq), np.bincount(o["query"], minlength=nq)
+    bad = gq != oq
+    ok_g = ~bad[g["query"]]
+    ok_o = ~bad[o["query"]]
+    du = np.abs(g["u"][ok_g, 0] - o["u1"][ok_o])
+    dv = np.abs(g["v"][ok_g, 0] - o["v1"][ok_o])
+    return {"compared": int(ok_o.sum()), "count_mismatch_queries": int(bad.sum()),
+            "ambiguous_queries": int(amb.sum()), "ambiguous_fraction": float(amb.mean()) if nq else 0.0,
+            "max_abs_du": float(du.max(initial=0.0)), "max_abs_dv": float(dv.max(initial=0.0)),
+            "p99_abs_du": float(np.percentile(du, 99)) if len(du) else 0.0,
+            "p99_abs_dv": float(np.percentile(dv, 99)) if len(dv) else 0.0}
+
+
+def cpu_baseline(args, mesh, light, ctx):
     """The FP64 oracle on the host cores over a bounded sample of the same
     workload: a seeded subset of the shading points, its own FP64 cone cull,
-    then the solve of every kept candidate."""
+    then the solve of every kept candidate; also on one core, and the GPU's
+    error against it on the same candidates."""
+    import torch
+
     sys.path.insert(0, os.path.join(ROOT, "oracle"))
     import oracle
-    from paper_2405_13409_amd import scenes
+    from paper_2405_13409_amd import scenes, spoly
 
     oracle.build()
-    cores = os.cpu_count() or 1
+    threads = oracle.set_threads(0)
     rng = np.random.default_rng(12345)
-    total_inst = 0.0
-    total_t = 0.0
     n_pts = 16
-    for ev, e0, e1 in (("R", 1.0, 1.0), ("T", 1.5, 1.0)):
-        allp = scenes.glints_large_points(ev, args.res)
-        t_budget = args.cpu_seconds / 2
-        spent = 0.0
-        while spent < t_budget:
-            idx = rng.choice(len(allp), n_pts, replace=False)
-            x0 = allp[idx]
-            t0 = time.perf_counter()
-            keep = oracle.cull_1bounce(mesh.P, mesh.N, mesh.tri, x0, light, e0, e1, 0.0)
-            j0, j2, jt = np.nonzero(keep)
-            oracle.solve_1bounce(mesh.P, mesh.N, mesh.tri, x0, light, j0, j2, jt, ev, e0, e1)
-            dt = time.perf_counter() - t0
-            spent += dt
-            total_t += dt
-            total_inst += len(jt)
-    return {"value": total_inst / total_t, "unit": "candidate solves/s", "cores": cores, "kind": "oracle",
-            "sample": f"{int(total_inst)} candidates from random {n_pts}-point batches of the same workload "
-                      f"(R and T, FP64 cull + solve, ~{args.cpu_seconds:.0f} s)"}
+    prec = spoly.SPOLY_FP32_POLISH64 if args.precision == "fp32" else spoly.SPOLY_FP64
+    dm = spoly.DeviceMesh(mesh.P, mesh.N, mesh.tri)
+    dl = spoly.DevicePoints(light)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).cuda()  # noqa: E731
+
+    def run(seconds):
+        inst, t_all, errs = 0, 0.0, {}
+        for ev, e0, e1 in (("R", 1.0, 1.0), ("T", 1.5, 1.0)):
+            allp = scenes.glints_large_points(ev, args.res)
+            spent = 0.0
+            while spent < seconds / 2:
+                x0 = allp[rng.choice(len(allp), n_pts, replace=False)]
+                t0 = time.perf_counter()
+                keep = oracle.cull_1bounce(mesh.P, mesh.N, mesh.tri, x0, light, e0, e1, 0.0)
+                j0, j2, jt = np.nonzero(keep)
+                orc, diag = oracle.solve_1bounce(mesh.P, mesh.N, mesh.tri, x0, light, j0, j2, jt, ev, e0, e1)
+                dt = time.perf_counter() - t0
+                spent += dt
+                t_all += dt
+                inst += len(jt)
+                if ev not in errs or errs[ev]["compared"] < 20000:
+                    g = ctx.solve_1bounce(dm, spoly.DevicePoints(x0), dl, dev(j0), dev(j2), dev(jt), ev, e0, e1,
+                                          prec)
+                    e = _errors_vs_oracle(g, orc, diag, len(jt))
+                    if ev in errs:
+                        a = errs[ev]
+                        for k in ("compared", "count_mismatch_queries", "ambiguous_queries"):
+                            a[k] += e[k]
+                        for k in ("max_abs_du", "max_abs_dv", "p99_abs_du", "p99_abs_dv"):
+                            a[k] = max(a[k], e[k])
+                    else:
+                        errs[ev] = e
+        return inst, t_all, errs
+
+    inst, t_all, errs = run(args.cpu_seconds)
+    oracle.set_threads(1)
+    inst1, t1, _ = run(max(2.0, args.cpu_seconds / 4))
+    oracle.set_threads(threads)
+    return {"value": inst / t_all, "unit": "candidate solves/s", "cores": threads, "kind": "oracle",
+            "cpu_model": _cpu_model(), "single_core_value": inst1 / t1,
+            "sample": f"{int(inst)} candidates from random {n_pts}-point batches of the same workload "
+                      f"(R and T, FP64 cull + solve, ~{args.cpu_seconds:.0f} s on {threads} threads; "
+                      f"{int(inst1)} more on one thread)",
+            "gpu_error_vs_oracle": {"precision": "fp32 bulk, fp64 polish" if args.precision == "fp32" else "fp64",
+                                    **{ev: errs[ev] for ev in errs}}}
 
 
 if __name__ == "__main__":

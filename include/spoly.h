@@ -93,8 +93,14 @@ typedef struct {
     double u_margin;       /* u is searched on [-m, 1-v+m] before the polish             */
     double dedup;          /* candidates closer than this in (u,v) are one solution      */
     int32_t polish_iters;  /* maximum FP64 Newton steps of the polish                    */
-    uint32_t flags;        /* reserved, 0                                                */
+    uint32_t flags;        /* SPOLY_FLAG_* bits; other bits must be 0                    */
 } spoly_params;
+
+/* spoly_params.flags */
+#define SPOLY_FLAG_FORCE_FP64   (1u << 1)  /* run every stage in double precision whatever */
+                                           /* the precision argument says                  */
+#define SPOLY_FLAG_STAGE_TIMES  (1u << 2)  /* one-vertex solve: record timing events       */
+                                           /* around its kernels (spoly_stage_times)       */
 
 /* One admissible chain.  For one vertex tri[1] = -1 and u[1] = v[1] = 0. */
 typedef struct {
@@ -120,6 +126,14 @@ void spoly_default_params(spoly_params *p);
  * range is widened because the sqrt approximation of Eq. eq_refr_rational
  * moves the approximate roots before the FP64 polish. */
 void spoly_tt_default_params(spoly_params *p);
+
+/* Durations in milliseconds of the kernels of the last spoly_solve_1bounce
+ * call on ctx that had SPOLY_FLAG_STAGE_TIMES set: reflection front, back,
+ * full list (3 values); refraction coefficients, isolation, back, full list
+ * (4 values).  ms [host, cap]; returns the number written, 0 if no such call
+ * was made, -1 on an argument or device error.  Waits for that call to finish.
+ * For measurement; the events are the context's own (hipEventCreate). */
+int32_t spoly_stage_times(spoly_ctx *ctx, float *ms, int32_t cap);
 
 /* Human-readable name of a status code (static storage). */
 const char *spoly_status_str(spoly_status s);

@@ -74,6 +74,11 @@ def lib():
         L.or_res_sign.argtypes = [P, ctypes.c_int32, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double]
         L.or_res_sign_paired.argtypes = [P, ctypes.c_int32, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double]
         L.or_maxsol.restype = ctypes.c_int
+        L.or_set_threads.argtypes = [ctypes.c_int]
+        L.or_set_threads.restype = ctypes.c_int
+        L.or_opcount_1bounce.argtypes = [P, P, P, P, P, P, P, P, ctypes.c_int64, ctypes.c_int32, ctypes.c_double,
+                                         ctypes.c_double, P, P]
+        L.or_opcount_2v.argtypes = [P, P, P, P, P, P, P, P, P, ctypes.c_int64, P, P, P, P, P]
         L.or_cull_tt.argtypes = [P, P, P, ctypes.c_int64, P, ctypes.c_int64, P, ctypes.c_int64, P,
                                  ctypes.c_double, P]
         L.or_cull_1bounce.argtypes = [P, P, P, ctypes.c_int64, P, ctypes.c_int64, P, ctypes.c_int64,
@@ -88,6 +93,11 @@ def _p(a: np.ndarray):
 
 def _c(a, dt):
     return np.ascontiguousarray(a, dtype=dt)
+
+
+def set_threads(n: int) -> int:
+    """Host threads of the parallel solves; returns the previous count."""
+    return int(lib().or_set_threads(int(n)))
 
 
 def maxsol() -> int:
@@ -205,6 +215,39 @@ def solve_tt(P, N, tri, x0s, x3s, q_x0, q_x3, q_t1, q_t2, eta=(1.0, 1.5, 1.0), p
     sols = out[sel]
     sols = sols[np.lexsort((sols["u1"], sols["v1"], sols["query"]))]
     return sols, diag
+
+
+def opcount_1bounce(P, N, tri, x0s, x2s, q_x0, q_x2, q_tri, event: str, eta0=1.0, eta1=1.0,
+                    params: Params | None = None) -> np.ndarray:
+    """Op counts [nq, 4] by stage (coefficients, elimination, root finding in v,
+    path phase) of each one-vertex query."""
+    L = lib()
+    P, N, x0s, x2s = (_c(a, np.float64) for a in (P, N, x0s, x2s))
+    tri, q_x0, q_x2, q_tri = (_c(a, np.int32) for a in (tri, q_x0, q_x2, q_tri))
+    nq = len(q_tri)
+    ops = np.zeros(4 * nq, dtype=np.uint64)
+    prm = params or default_params(False)
+    L.or_opcount_1bounce(_p(P), _p(N), _p(tri), _p(x0s), _p(x2s), _p(q_x0), _p(q_x2), _p(q_tri), nq,
+                         1 if event == "T" else 0, eta0, eta1, ctypes.byref(prm), _p(ops))
+    return ops.reshape(nq, 4)
+
+
+def opcount_2v(P, N, tri, x0s, x3s, q_x0, q_x3, q_t1, q_t2, chain: str, eta=(1.0, 1.5, 1.0),
+               params: Params | None = None, fit: SqrtFit | None = None) -> np.ndarray:
+    """Op counts [nq, 4] by stage (coefficients, scan samples, bisection
+    samples, path phase) of each two-vertex query."""
+    L = lib()
+    P, N, x0s, x3s = (_c(a, np.float64) for a in (P, N, x0s, x3s))
+    tri, q_x0, q_x3, q_t1, q_t2 = (_c(a, np.int32) for a in (tri, q_x0, q_x3, q_t1, q_t2))
+    nq = len(q_t1)
+    ops = np.zeros(4 * nq, dtype=np.uint64)
+    eta = _c(eta, np.float64)
+    ch = _chain(chain)
+    prm = params or default_params(True)
+    fit = fit or default_sqrt_fit()
+    L.or_opcount_2v(_p(P), _p(N), _p(tri), _p(x0s), _p(x3s), _p(q_x0), _p(q_x3), _p(q_t1), _p(q_t2), nq,
+                    _p(eta), _p(ch), ctypes.byref(fit), ctypes.byref(prm), _p(ops))
+    return ops.reshape(nq, 4)
 
 
 def coeffs_1bounce(P, N, tri, t: int, x0, x2, event: str, eta0=1.0, eta1=1.0):

@@ -34,12 +34,29 @@
  */
 #define _GNU_SOURCE
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
 #define OR_MAXSOL 16
+
+/* ------------------------------------------------------------------ op counter
+ * Floating-point operations of the method, by stage, counted in the
+ * polynomial and root-finding primitives (one per add, multiply or divide,
+ * two per multiply-add) and as fixed per-call figures in the short geometric
+ * routines.  Stages: 0 coefficient phase, 1 elimination (one vertex: Bezout
+ * matrix and Laplace expansion; two vertices: the det-sign samples of the
+ * scan), 2 root finding in v (one vertex: isolation; two vertices: the
+ * bisection samples), 3 path phase (u roots, polish, validation).  The
+ * Laplace expansion counts each minor once (memoised cost) and a bisection
+ * counts its steps down to the paper's 1e-9 only; diagnostics count nothing.
+ * Per thread; read by or_opcount_*.                                         */
+static __thread uint64_t g_ops[4];
+static __thread int g_stage;
+static __thread int g_count = 1;
+#define OPS(n) (g_ops[g_stage] += g_count ? (uint64_t)(n) : 0u)
 
 /* ------------------------------------------------------------------ params */
 typedef struct {
@@ -139,6 +156,7 @@ static bp bp_mul(arena *A, bp a, bp b)
             for (int k = 0; k <= b.d; ++k)
                 for (int l = 0; k + l <= b.d; ++l)
                     r.c[(i + k) * (r.d + 1) + (j + l)] += x * b.c[k * (b.d + 1) + l];
+            OPS(2 * (b.d + 1) * (b.d + 2) / 2);
         }
     return r;
 }
@@ -149,6 +167,7 @@ static bp bp_lc(arena *A, double sa, bp a, double sb, bp b)
     for (int i = 0; i <= r.d; ++i)
         for (int j = 0; i + j <= r.d; ++j)
             r.c[i * (r.d + 1) + j] = sa * bp_at(a, i, j) + sb * bp_at(b, i, j);
+    OPS(3 * (r.d + 1) * (r.d + 2) / 2);
     return r;
 }
 static bp bp_add(arena *A, bp a, bp b) { return bp_lc(A, 1.0, a, 1.0, b); }
@@ -159,6 +178,7 @@ static bp bp_scale(arena *A, bp a, double s) { return bp_lc(A, s, a, 0.0, a); }
 static void bp_eval3(bp p, double u, double v, double *f, double *fu, double *fv)
 {
     double s = 0, su = 0, sv = 0;
+    OPS(8 * (p.d + 1) * (p.d + 2) / 2);
     for (int i = 0; i <= p.d; ++i)
         for (int j = 0; i + j <= p.d; ++j) {
             double c = p.c[i * (p.d + 1) + j];
@@ -223,6 +243,7 @@ static up up_mul(arena *A, up a, up b)
     up r = up_new(A, a.d + b.d);
     for (int i = 0; i <= a.d; ++i)
         for (int j = 0; j <= b.d; ++j) r.c[i + j] += a.c[i] * b.c[j];
+    OPS(2 * (a.d + 1) * (b.d + 1));
     return r;
 }
 static up up_lc(arena *A, double sa, up a, double sb, up b)
@@ -231,10 +252,12 @@ static up up_lc(arena *A, double sa, up a, double sb, up b)
     up r = up_new(A, d);
     for (int k = 0; k <= d; ++k)
         r.c[k] = (k <= a.d ? sa * a.c[k] : 0.0) + (k <= b.d ? sb * b.c[k] : 0.0);
+    OPS(3 * (d + 1));
     return r;
 }
 static double up_eval(const double *c, int d, double v)
 {
+    OPS(2 * (d + 1));
     double s = 0.0;
     for (int k = d; k >= 0; --k) s = s * v + c[k];
     return s;
@@ -270,9 +293,15 @@ static void bezout_poly(arena *A, const up *ac, const up *bc, int n, up *M /* n*
 
 /* Laplace (cofactor) expansion along the first remaining row, Sec. 5.2.
  * Rows r..n-1, columns given by `mask`.                                      */
+static __thread unsigned char g_minor_seen[1 << 12];
 static up laplace(arena *A, const up *M, int n, int r, unsigned mask)
 {
     if (r == n) { up one = up_new(A, 0); one.c[0] = 1.0; return one; }
+    /* op counter: a minor (rows r.., columns `mask`) is counted once */
+    int saved = g_count;
+    if (r == 0) memset(g_minor_seen, 0, sizeof(g_minor_seen));
+    if (g_minor_seen[mask]) g_count = 0;
+    g_minor_seen[mask] = 1;
     up acc = up_new(A, -1);
     int pos = 0;
     for (int j = 0; j < n; ++j) {
@@ -285,6 +314,7 @@ static up laplace(arena *A, const up *M, int n, int r, unsigned mask)
         }
         ++pos;
     }
+    g_count = saved;
     return acc;
 }
 
@@ -297,11 +327,14 @@ static int sgn(double x) { return x < 0.0 ? -1 : 1; }
 
 static double bisect_full(const double *c, int d, double l, double r, int sl)
 {
+    int saved = g_count;
     for (int it = 0; it < 2000; ++it) {
         double m = 0.5 * (l + r);
         if (!(m > l && m < r)) break;
+        if (!(r - l > 1e-9)) g_count = 0;   /* op counter: the paper's 1e-9 */
         if (sgn(up_eval(c, d, m)) == sl) l = m; else r = m;
     }
+    g_count = saved;
     return 0.5 * (l + r);
 }
 
@@ -313,6 +346,7 @@ static int isolate(arena *A, const double *c, int d, double lo, double hi, doubl
     if (d >= 2) {
         double *dc = (double *)ar_alloc(A, sizeof(double) * (size_t)d);
         for (int k = 1; k <= d; ++k) dc[k - 1] = k * c[k];
+        OPS(d);
         crit = (double *)ar_alloc(A, sizeof(double) * (size_t)d);
         nc = isolate(A, dc, d - 1, lo, hi, crit, d);
     }
@@ -340,6 +374,7 @@ static int isolate(arena *A, const double *c, int d, double lo, double hi, doubl
  * reflection, < 0 for refraction.                                             */
 static int vertex_law(v3 xp, v3 x, v3 xn, v3 nrm, double eta_in, double eta_out, int refract, double *res)
 {
+    OPS(70);
     double ln = vlen(nrm);
     if (!(ln > 1e-12)) { *res = 1e300; return 0; }
     v3 nh = vmul(nrm, 1.0 / ln);
@@ -493,6 +528,7 @@ static int polish_ab(bp a, bp b, int iters, double *pu, double *pv)
         bp_eval3(a, u, v, &fa, &au, &av);
         bp_eval3(b, u, v, &fb, &bu, &bvv);
         double det = au * bvv - av * bu;
+        OPS(12);
         if (!(det != 0.0) || !isfinite(det)) break;
         double du = (fa * bvv - av * fb) / det;
         double dv = (au * fb - fa * bu) / det;
@@ -521,6 +557,7 @@ static void solve_1b(arena *A, const tri_t *T, v3 x0, v3 x2, int refract, double
     dg->tangency = 1e300;
     if (T->flat) dg->flags |= OR_F_FLAT1;
     bp a, b;
+    g_stage = 0;
     int nb = coeffs_1b(A, T, x0, x2, refract, eta0, eta1, &a, &b, &dg->flags);
     int ma = numeric_udeg(a, a.d);
     nb = numeric_udeg(b, nb);
@@ -531,6 +568,7 @@ static void solve_1b(arena *A, const tri_t *T, v3 x0, v3 x2, int refract, double
     up *bc = (up *)ar_alloc(A, sizeof(up) * (size_t)(n + 1));
     for (int i = 0; i <= n; ++i) { ac[i] = bp_ucoef(A, a, i); bc[i] = bp_ucoef(A, b, i); }
     up *M = (up *)ar_alloc(A, sizeof(up) * (size_t)(n * n));
+    g_stage = 1;
     bezout_poly(A, ac, bc, n, M);
     up r = laplace(A, M, n, 0, (1u << n) - 1u);
     double scale = 0.0;
@@ -541,7 +579,9 @@ static void solve_1b(arena *A, const tri_t *T, v3 x0, v3 x2, int refract, double
         *nout = 0;
         return;
     }
-    /* tangency diagnostic at the critical points of r */
+    /* tangency diagnostic at the critical points of r (not part of the method) */
+    int saved = g_count;
+    g_count = 0;
     if (r.d >= 2) {
         double *dc = (double *)ar_alloc(A, sizeof(double) * (size_t)r.d);
         for (int k = 1; k <= r.d; ++k) dc[k - 1] = k * r.c[k];
@@ -550,8 +590,11 @@ static void solve_1b(arena *A, const tri_t *T, v3 x0, v3 x2, int refract, double
         for (int k = 0; k < ncr; ++k)
             dg->tangency = fmin(dg->tangency, fabs(up_eval(r.c, r.d, crit[k])) / scale);
     }
+    g_count = saved;
+    g_stage = 2;
     double vr[64];
     int nv = isolate(A, r.c, r.d, 0.0, 1.0, vr, 64);
+    g_stage = 3;
     dg->n_vroots = nv;
     for (int k = 1; k < nv; ++k) dg->min_gap = fmin(dg->min_gap, vr[k] - vr[k - 1]);
     for (int k = 0; k < nv; ++k) {
@@ -773,11 +816,13 @@ static int det_sign_at(arena *A, bp a, bp b, int n, double v)
         if (i <= b.d) for (int j = b.d - i; j >= 0; --j) bi[i] = bi[i] * v + b.c[i * (b.d + 1) + j];
     }
     double *M = (double *)ar_alloc(A, sizeof(double) * (size_t)n * (size_t)n);
+    OPS(2 * (a.d + 1) * (a.d + 2) / 2 + 2 * (b.d + 1) * (b.d + 2) / 2);
     for (int i = 0; i < n; ++i)
         for (int j = 0; j < n; ++j) {
             double s = 0.0;
             int kmax = i < n - 1 - j ? i : n - 1 - j;
             for (int k = 0; k <= kmax; ++k) s += ai[i - k] * bi[j + 1 + k] - bi[i - k] * ai[j + 1 + k];
+            OPS(4 * (kmax + 1));
             M[i * n + j] = s;
         }
     int sign = 1;
@@ -794,8 +839,10 @@ static int det_sign_at(arena *A, bp a, bp b, int n, double v)
         if (piv < 0) sign = -sign;
         for (int i = k + 1; i < n; ++i) {
             double l = M[i * n + k] / piv;
+            OPS(1);
             if (l == 0.0) continue;
             for (int j = k + 1; j < n; ++j) M[i * n + j] -= l * M[k * n + j];
+            OPS(2 * (n - k - 1));
         }
     }
     A->top = mark;
@@ -808,6 +855,7 @@ static int det_sign_at(arena *A, bp a, bp b, int n, double v)
 static int trace_x2(const tri_t *T1, const tri_t *T2, v3 x0, double u1, double v1, int ev1, double etap,
                     double *u2, double *v2, v3 *x1o, v3 *x2o)
 {
+    OPS(90);
     v3 x1 = tri_x(T1, u1, v1);
     v3 n = vnorm(tri_n(T1, u1, v1));
     v3 di = vnorm(vsub(x1, x0));
@@ -842,6 +890,7 @@ static int tt_residual(const tri_t *T1, const tri_t *T2, v3 x0, v3 x3, const dou
 {
     double u2, v2; v3 x1, x2;
     if (!trace_x2(T1, T2, x0, u1, v1, ev1, eta[0] / eta[1], &u2, &v2, &x1, &x2)) return 0;
+    OPS(75);
     v3 n2 = vnorm(tri_n(T2, u2, v2));
     v3 wi = vnorm(vsub(x1, x2)), wo = vnorm(vsub(x3, x2));
     v3 h = vnorm(vadd(vmul(wi, eta[1]), vmul(wo, eta[2])));
@@ -867,6 +916,7 @@ static int polish_tt(const tri_t *T1, const tri_t *T2, v3 x0, v3 x3, const doubl
         if (!tt_residual(T1, T2, x0, x3, eta, ev1, ta, tb, u - h, v, Fu0)) return 0;
         if (!tt_residual(T1, T2, x0, x3, eta, ev1, ta, tb, u, v + h, Fv1)) return 0;
         if (!tt_residual(T1, T2, x0, x3, eta, ev1, ta, tb, u, v - h, Fv0)) return 0;
+        OPS(24);
         double J00 = (Fu1[0] - Fu0[0]) / (2 * h), J10 = (Fu1[1] - Fu0[1]) / (2 * h);
         double J01 = (Fv1[0] - Fv0[0]) / (2 * h), J11 = (Fv1[1] - Fv0[1]) / (2 * h);
         double det = J00 * J11 - J01 * J10;
@@ -947,6 +997,8 @@ static int res_sign_paired(arena *A, bp a, int ma, bp b, double v)
     size_t mark = A->top;
     double *ai = (double *)ar_alloc(A, sizeof(double) * (size_t)(ma + 1));
     double *bi = (double *)ar_alloc(A, sizeof(double) * (size_t)(b.d + 1));
+    /* a_i(v), b_i(v) by Horner, the root bound and the scaling to [-1, 1] */
+    OPS((a.d + 1) * (a.d + 2) + (b.d + 1) * (b.d + 2) + 5 * ma + 2);
     for (int i = 0; i <= ma; ++i) {
         double s = 0.0;
         for (int j = a.d - i; j >= 0; --j) s = s * v + a.c[i * (a.d + 1) + j];
@@ -970,9 +1022,11 @@ static int res_sign_paired(arena *A, bp a, int ma, bp b, double v)
     int nr = isolate(A, w, ma, -1.0, 1.0, roots, 64);
     for (int k = 0; k < nr; ++k) {
         double al = roots[k] * B;
+        OPS(1);
         if (k + 1 < nr && roots[k + 1] * B - al <= 1e-4 * fmax(1.0, fabs(al))) { ++k; continue; }
         double s = 0.0;
         for (int i = b.d; i >= 0; --i) s = s * al + bi[i];
+        OPS(2 * (b.d + 1));
         if (s < 0.0) sign = -sign;
     }
     A->top = mark;
@@ -988,6 +1042,7 @@ static void solve_2v(arena *A, const tri_t *T1, const tri_t *T2, v3 x0, v3 x3, c
     if (T1->flat) dg->flags |= OR_F_FLAT1;
     if (T2->flat) dg->flags |= OR_F_FLAT2;
     bp a, b;
+    g_stage = 0;
     int nb = coeffs_2v(A, T1, T2, x0, x3, eta, ev1, ev2, fit, &a, &b, &dg->flags);
     int ma = numeric_udeg(a, a.d);
     nb = numeric_udeg(b, nb);
@@ -998,7 +1053,9 @@ static void solve_2v(arena *A, const tri_t *T1, const tri_t *T2, v3 x0, v3 x3, c
     int *sg = (int *)ar_alloc(A, sizeof(int) * (size_t)(P + 1));
 #define DETSIGN(vv) (prm->det_method == 2 ? res_sign_paired(A, a, ma, b, (vv)) : \
                      prm->det_method == 1 ? res_sign_product(A, a, ma, b, n, (vv)) : det_sign_at(A, a, b, n, (vv)))
+    g_stage = 1;
     for (int j = 0; j <= P; ++j) sg[j] = DETSIGN((double)j / P);
+    g_stage = 2;
     double vr[OR_MAXSOL * 8];
     int nv = 0;
     for (int j = 0; j < P; ++j) {
@@ -1013,6 +1070,7 @@ static void solve_2v(arena *A, const tri_t *T1, const tri_t *T2, v3 x0, v3 x3, c
     }
     dg->n_vroots = nv;
     for (int k = 1; k < nv; ++k) dg->min_gap = fmin(dg->min_gap, vr[k] - vr[k - 1]);
+    g_stage = 3;
     int nsol = 0;
     double etap = eta[0] / eta[1];
     for (int k = 0; k < nv; ++k) {
@@ -1023,6 +1081,7 @@ static void solve_2v(arena *A, const tri_t *T1, const tri_t *T2, v3 x0, v3 x3, c
             for (int j = a.d - i; j >= 0; --j) s = s * v + a.c[i * (a.d + 1) + j];
             auc[i] = s;
         }
+        OPS((a.d + 1) * (a.d + 2));
         double ur[64];
         int nu = isolate(A, auc, ma, -prm->u_margin, 1.0 - v + prm->u_margin, ur, 64);
         for (int m = 0; m < nu; ++m) {
@@ -1146,6 +1205,61 @@ int or_res_sign_paired(const double *a_in, int32_t da, const double *b_in, int32
     int s = res_sign_paired(&A, a, ma, b, v);
     free(A.base);
     return s;
+}
+
+/* Op counts by stage (ops[4 q + s]) of each query, solved one at a time on
+ * the calling thread with the same arithmetic as or_solve_1bounce.         */
+int or_opcount_1bounce(const double *P, const double *N, const int32_t *tri,
+                       const double *x0s, const double *x2s,
+                       const int32_t *q_x0, const int32_t *q_x2, const int32_t *q_tri, int64_t nq,
+                       int32_t refract, double eta0, double eta1, const or_params *prm, uint64_t *ops)
+{
+    arena A;
+    A.cap = (size_t)8 << 20; A.top = 0; A.base = (char *)malloc(A.cap);
+    or_sol out[OR_MAXSOL];
+    for (int64_t q = 0; q < nq; ++q) {
+        A.top = 0;
+        memset(g_ops, 0, sizeof(g_ops));
+        g_count = 1;
+        int32_t cnt; or_diag dg;
+        tri_t T = load_tri(P, N, tri, q_tri[q]);
+        solve_1b(&A, &T, vload(x0s, q_x0[q]), vload(x2s, q_x2[q]), refract, eta0, eta1, prm, (int32_t)q,
+                 out, &cnt, &dg);
+        for (int k = 0; k < 4; ++k) ops[4 * q + k] = g_ops[k];
+    }
+    free(A.base);
+    return 0;
+}
+
+int or_opcount_2v(const double *P, const double *N, const int32_t *tri,
+                  const double *x0s, const double *x3s,
+                  const int32_t *q_x0, const int32_t *q_x3, const int32_t *q_t1, const int32_t *q_t2, int64_t nq,
+                  const double *eta, const int32_t *chain, const or_sqrtfit *fit, const or_params *prm,
+                  uint64_t *ops)
+{
+    arena A;
+    A.cap = (size_t)64 << 20; A.top = 0; A.base = (char *)malloc(A.cap);
+    or_sol out[OR_MAXSOL];
+    for (int64_t q = 0; q < nq; ++q) {
+        A.top = 0;
+        memset(g_ops, 0, sizeof(g_ops));
+        g_count = 1;
+        int32_t cnt; or_diag dg;
+        tri_t T1 = load_tri(P, N, tri, q_t1[q]), T2 = load_tri(P, N, tri, q_t2[q]);
+        solve_2v(&A, &T1, &T2, vload(x0s, q_x0[q]), vload(x3s, q_x3[q]), eta, chain[0], chain[1], fit, prm,
+                 (int32_t)q, out, &cnt, &dg);
+        for (int k = 0; k < 4; ++k) ops[4 * q + k] = g_ops[k];
+    }
+    free(A.base);
+    return 0;
+}
+
+/* host threads of the parallel solves (OpenMP); returns the previous count */
+int or_set_threads(int n)
+{
+    int old = omp_get_max_threads();
+    if (n > 0) omp_set_num_threads(n);
+    return old;
 }
 
 int or_maxsol(void) { return OR_MAXSOL; }

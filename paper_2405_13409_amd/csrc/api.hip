@@ -27,6 +27,8 @@ struct spoly_ctx {
     int64_t ob_cap;
     void* ob_rblock;       // r(v) of the candidates listed for isolation, list and status
     int64_t ob_rbytes;
+    hipEvent_t stage_ev[5];  // timing events of the last one-vertex solve with SPOLY_FLAG_STAGE_TIMES
+    int stage_n;             // kernels timed by stage_ev (0: none yet)
 };
 
 namespace {
@@ -107,7 +109,21 @@ void spoly_ctx_destroy(spoly_ctx* ctx)
     if (ctx->pw_block) (void)hipFree(ctx->pw_block);
     if (ctx->ob_block) (void)hipFree(ctx->ob_block);
     if (ctx->ob_rblock) (void)hipFree(ctx->ob_rblock);
+    if (ctx->stage_ev[0])
+        for (int i = 0; i < 5; ++i) (void)hipEventDestroy(ctx->stage_ev[i]);
     std::free(ctx);
+}
+
+int32_t spoly_stage_times(spoly_ctx* ctx, float* ms, int32_t cap)
+{
+    if (!ctx || (cap > 0 && !ms) || cap < 0) return -1;
+    if (ctx->stage_n == 0) return 0;
+    if (hipSetDevice(ctx->device) != hipSuccess) return -1;
+    if (hipEventSynchronize(ctx->stage_ev[ctx->stage_n]) != hipSuccess) return -1;
+    int32_t n = ctx->stage_n < cap ? ctx->stage_n : cap;
+    for (int32_t i = 0; i < n; ++i)
+        if (hipEventElapsedTime(&ms[i], ctx->stage_ev[i], ctx->stage_ev[i + 1]) != hipSuccess) return -1;
+    return n;
 }
 
 // Item list between the two phases of the one-vertex solve, and for
@@ -225,13 +241,22 @@ spoly_status spoly_solve_1bounce(spoly_ctx* ctx, const spoly_mesh* mesh, const s
     spoly_status st = ob_args(mesh, x0s, x2s, q_x0, q_x2, q_tri, n_queries, ev, eta0, eta1, prec, params, out,
                               out_capacity, out_count, counters, diag_q, A);
     if (st != SPOLY_OK) return st;
+    if (params->flags & SPOLY_FLAG_FORCE_FP64) prec = SPOLY_FP64;
     if (hipSetDevice(ctx->device) != hipSuccess) return SPOLY_E_DEVICE;
     // the refraction front lists r(v) (13 doubles) of candidates between its two kernels
     const size_t coef_bytes = ev == SPOLY_T ? 13 * 8 : 0;
     st = ensure_ob_items(ctx, n_queries, coef_bytes, A);
     if (st != SPOLY_OK) return st;
+    hipEvent_t* evs = nullptr;
+    if (params->flags & SPOLY_FLAG_STAGE_TIMES) {
+        if (!ctx->stage_ev[0])
+            for (int i = 0; i < 5; ++i)
+                if (hipEventCreate(&ctx->stage_ev[i]) != hipSuccess) return SPOLY_E_DEVICE;
+        evs = ctx->stage_ev;
+        ctx->stage_n = n_queries > 0 ? (ev == SPOLY_T ? 4 : 3) : 0;
+    }
     return dev_err(spoly::launch_onebounce_2phase(A, int(ev), int(prec), ctx->cus * 4,
-                                                  static_cast<hipStream_t>(stream)));
+                                                  static_cast<hipStream_t>(stream), evs));
 }
 
 }  // extern "C"
@@ -254,6 +279,8 @@ static spoly_status ob_args(const spoly_mesh* mesh, const spoly_points* x0s, con
     if (!(params->tau > 0.0) || !(params->iso_eps > 0.0) || params->polish_iters < 0 || !(params->u_margin >= 0.0) ||
         !(params->dedup >= 0.0))
         return SPOLY_E_INVALID_ARG;
+    if (params->flags & ~(SPOLY_FLAG_FORCE_FP64 | SPOLY_FLAG_STAGE_TIMES)) return SPOLY_E_INVALID_ARG;
+    if (params->flags & SPOLY_FLAG_FORCE_FP64) prec = SPOLY_FP64;
     A.px = mesh->px; A.py = mesh->py; A.pz = mesh->pz;
     A.nx = mesh->nx; A.ny = mesh->ny; A.nz = mesh->nz;
     A.tri = mesh->tri;
@@ -325,6 +352,7 @@ spoly_status spoly_solve_1bounce_noalloc(const spoly_mesh* mesh, const spoly_poi
     spoly_status st = ob_args(mesh, x0s, x2s, q_x0, q_x2, q_tri, n_queries, ev, eta0, eta1, prec, params, out,
                               out_capacity, out_count, counters, diag_q, A);
     if (st != SPOLY_OK) return st;
+    if (params->flags & SPOLY_FLAG_FORCE_FP64) prec = SPOLY_FP64;
     const int64_t max_q = ev == SPOLY_T ? SPOLY_NOALLOC_MAX_QUERIES_T : SPOLY_NOALLOC_MAX_QUERIES_R;
     if (n_queries > max_q) return SPOLY_E_CAPACITY;
     ScratchSlot slot;

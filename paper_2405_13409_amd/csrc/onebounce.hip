@@ -11,6 +11,14 @@ namespace spoly {
 constexpr int kMaxLaneSol = 4;
 constexpr double kNearDoubleU = 1e-3;   // u-root pairs closer than this are tried from their midpoint
 constexpr double kRefineWindow = 0.005; // FP32 reflection: refine v when the nearest u misses the triangle by less
+// FP32 reflection: refine v when a(u)|v has a complex u pair this close to the
+// real axis with its real part in (or this close to) the triangle.  Near a fold
+// of the coplanarity curve (a double u root) the pair's imaginary part grows
+// like the square root of the error in v: a v error of 1e-5, typical of the
+// FP32 resultant, can open a pair 0.05 wide at a solution 1e-6 from the fold.
+// At the roots of the FP64 resultant such pairs do not occur (none among
+// 8245 roots of 30000 glints candidates), so the hand-offs stay rare.
+constexpr double kComplexWindow = 0.1;
 // FP32 reflection: a candidate whose r(v) comes within this fraction of sum |r_k|
 // of zero at v = 0, v = 1 or a critical point in [0,1] without the isolation
 // seeing a sign change there (or with one that rounding may have moved) is
@@ -462,8 +470,8 @@ __device__ __forceinline__ double refine_v64(const Geo& g, double v)
 
 // One root v of r: u from a(u)|v, FP64 polish, closed-triangle and path-space checks.
 // Real u roots of a(u)|v (ascending) from the FP64 coefficients; `near`
-// reports a complex pair within kRefineWindow of the real axis (the case a
-// slightly wrong v produces).
+// reports a complex pair within kComplexWindow of the real axis over the
+// triangle (the case a slightly wrong v produces near a fold).
 template <int F>
 __device__ __forceinline__ int u_roots(const P2<double, 1 + F>& a64, double v, double (&us)[2], bool& near)
 {
@@ -489,7 +497,9 @@ __device__ __forceinline__ int u_roots(const P2<double, 1 + F>& a64, double v, d
                 us[1] = fmax(r1, r2);
                 return 2;
             }
-            near = -disc <= 4.0 * kRefineWindow * kRefineWindow * qa * qa;
+            const double re = -qb / (2.0 * qa);
+            near = -disc <= 4.0 * kComplexWindow * kComplexWindow * qa * qa && re >= -kComplexWindow &&
+                   re <= 1.0 - v + kComplexWindow;
             if (-disc <= kNearDoubleU * kNearDoubleU * qa * qa) {
                 // The two u roots are within kNearDoubleU of each other or a
                 // complex pair that close to the real axis: v is known only to
@@ -1036,10 +1046,17 @@ __global__ void k_zero_items(unsigned long long* p)
     p[2] = 0ull;   // refraction: candidates listed for isolation
 }
 
-hipError_t launch_onebounce_2phase(const OneBounceArgs& A, int ev, int prec, int back_blocks, hipStream_t stream)
+hipError_t launch_onebounce_2phase(const OneBounceArgs& A, int ev, int prec, int back_blocks, hipStream_t stream,
+                                   hipEvent_t* stage_events)
 {
     if (A.nq <= 0) return hipSuccess;
     if (A.items_cap < A.nq || (ev == SPOLY_T && !A.rlist)) return hipErrorInvalidValue;
+    int stage = 0;
+    auto mark = [&]() {
+        if (stage_events) (void)hipEventRecord(stage_events[stage], stream);
+        ++stage;
+    };
+    mark();
     hipLaunchKernelGGL(k_zero_items, dim3(1), dim3(1), 0, stream, A.items_count);
     const dim3 block(256), grid(unsigned((A.nq + 255) / 256));
     const dim3 bgrid(unsigned(back_blocks > 0 ? back_blocks : 1));
@@ -1047,17 +1064,27 @@ hipError_t launch_onebounce_2phase(const OneBounceArgs& A, int ev, int prec, int
     // Refraction always runs in FP64 (see launch_onebounce).
     if (ev == SPOLY_R && prec == SPOLY_FP64) {
         hipLaunchKernelGGL((k_ob_front<double, SPOLY_R>), grid, block, 0, stream, A);
+        mark();
         hipLaunchKernelGGL((k_ob_back<SPOLY_R>), bgrid, block, 0, stream, A);
+        mark();
         hipLaunchKernelGGL((k_ob_full<SPOLY_R>), fgrid, block, 0, stream, A);
+        mark();
     } else if (ev == SPOLY_R) {
         hipLaunchKernelGGL((k_ob_front<float, SPOLY_R>), grid, block, 0, stream, A);
+        mark();
         hipLaunchKernelGGL((k_ob_back<SPOLY_R>), bgrid, block, 0, stream, A);
+        mark();
         hipLaunchKernelGGL((k_ob_full<SPOLY_R>), fgrid, block, 0, stream, A);
+        mark();
     } else {
         hipLaunchKernelGGL((k_ob_coef<double, SPOLY_T>), grid, block, 0, stream, A);
+        mark();
         hipLaunchKernelGGL((k_ob_iso<double, SPOLY_T>), bgrid, block, 0, stream, A);
+        mark();
         hipLaunchKernelGGL((k_ob_back<SPOLY_T>), bgrid, block, 0, stream, A);
+        mark();
         hipLaunchKernelGGL((k_ob_full<SPOLY_T>), fgrid, block, 0, stream, A);
+        mark();
     }
     return hipGetLastError();
 }

@@ -47,7 +47,10 @@ hipError_t launch_onebounce(const OneBounceArgs& A, int ev, int prec, hipStream_
 // kernel (back_blocks blocks) solves u, polishes and validates the items with
 // full waves, and a last kernel solves the rare candidates of the full list
 // from scratch.
-hipError_t launch_onebounce_2phase(const OneBounceArgs& A, int ev, int prec, int back_blocks, hipStream_t stream);
+// stage_events (optional, 5 events): recorded before the first kernel and after
+// each kernel of the phase sequence (reflection: 3 kernels, refraction: 4).
+hipError_t launch_onebounce_2phase(const OneBounceArgs& A, int ev, int prec, int back_blocks, hipStream_t stream,
+                                   hipEvent_t* stage_events = nullptr);
 
 struct CullArgs {
     const float4* tri_cone;   // per triangle: (centroid.xyz, radius), (axis.xyz, half angle)

@@ -536,6 +536,41 @@ __device__ __forceinline__ double root_k_upper(double x, int k)
 // rounding noise.
 constexpr double kPairGap = 1e-4;
 
+// Product of sgn b(x B, v) over the real roots x in [-1, 1] of the scaled
+// a(., v) (coefficients c, degree at most D), near-double pairs left out.
+template <int D>
+__device__ __forceinline__ int sign_over_roots(const TTGeo& g, const double (&c)[kDA + 1], double B, double v)
+{
+    double cc[D + 1];
+#pragma unroll
+    for (int k = 0; k <= D; ++k) cc[k] = c[k];
+    double rt[D + 1];
+    unsigned okm = iso_level<D, D>(cc, -1.0, 1.0, rt);
+    // roots in ascending order; a root waits in `p` until the next one shows
+    // whether the two form a near-double pair (left out of the product)
+    int s = 1;
+    bool has_p = false;
+    double p = 0.0;
+    while (okm) {
+        const int k = __builtin_ctz(okm);
+        okm &= okm - 1u;
+        double x = 0.0;
+#pragma unroll
+        for (int j = 0; j <= D; ++j)
+            if (j == k) x = rt[j];
+        x *= B;
+        if (has_p && x - p <= kPairGap * fmax(1.0, fabs(p))) {
+            has_p = false;
+            continue;
+        }
+        if (has_p && tt_b_eval(g, p, v) < 0.0) s = -s;
+        p = x;
+        has_p = true;
+    }
+    if (has_p && tt_b_eval(g, p, v) < 0.0) s = -s;
+    return s;
+}
+
 // sign of det R(v) (up to a constant sign): product of sgn b over the real roots of a(., v)
 __device__ int tt_det_sign(const TTGeo& g, const double* __restrict__ Ac, int da, int ma, double v)
 {
@@ -563,31 +598,7 @@ __device__ int tt_det_sign(const TTGeo& g, const double* __restrict__ Ac, int da
         c[k] *= pw;
         pw *= B;
     }
-    double rt[kDA + 1];
-    unsigned okm = iso_level<kDA, kDA>(c, -1.0, 1.0, rt);
-    // roots in ascending order; a root waits in `p` until the next one shows
-    // whether the two form a near-double pair (left out of the product)
-    int s = 1;
-    bool has_p = false;
-    double p = 0.0;
-    while (okm) {
-        const int k = __builtin_ctz(okm);
-        okm &= okm - 1u;
-        double x = 0.0;
-#pragma unroll
-        for (int j = 0; j <= kDA; ++j)
-            if (j == k) x = rt[j];
-        x *= B;
-        if (has_p && x - p <= kPairGap * fmax(1.0, fabs(p))) {
-            has_p = false;
-            continue;
-        }
-        if (has_p && tt_b_eval(g, p, v) < 0.0) s = -s;
-        p = x;
-        has_p = true;
-    }
-    if (has_p && tt_b_eval(g, p, v) < 0.0) s = -s;
-    return s;
+    return ma <= 8 ? sign_over_roots<8>(g, c, B, v) : sign_over_roots<kDA>(g, c, B, v);
 }
 
 // ------------------------------------------------------------------ path phase (exact constraints, FP64)

@@ -27,7 +27,9 @@ assert SOLUTION_DTYPE.itemsize == 56
 EXPORTED = ("spoly_ctx_create", "spoly_ctx_destroy", "spoly_default_params", "spoly_status_str",
             "spoly_cull_1bounce", "spoly_solve_1bounce", "spoly_cull_2bounce", "spoly_solve_nbounce",
             "spoly_prune_score", "spoly_pruner_fwd_bwd", "spoly_pruner_step", "spoly_pruner_features",
-            "spoly_solve_mixed", "spoly_tt_default_params", "spoly_solve_1bounce_noalloc")
+            "spoly_solve_mixed", "spoly_tt_default_params", "spoly_solve_1bounce_noalloc", "spoly_stage_times")
+SPOLY_FLAG_FORCE_FP64 = 1 << 1
+SPOLY_FLAG_STAGE_TIMES = 1 << 2
 PRUNER_NPARAMS = 38657
 
 
@@ -78,6 +80,8 @@ def load_library(path: str = LIB_PATH):
     L.spoly_tt_default_params.restype = None
     L.spoly_status_str.argtypes = [ctypes.c_int]
     L.spoly_status_str.restype = ctypes.c_char_p
+    L.spoly_stage_times.argtypes = [P, P, ctypes.c_int32]
+    L.spoly_stage_times.restype = ctypes.c_int32
     L.spoly_cull_1bounce.argtypes = [P, ctypes.POINTER(Mesh), ctypes.POINTER(Points), ctypes.POINTER(Points), D, D, D,
                                      P, P, P, I64, P, P]
     L.spoly_cull_1bounce.restype = ctypes.c_int
@@ -201,6 +205,15 @@ class Context:
             if n <= cap:
                 return qx0[:n], qx2[:n], qt[:n]
             cap = n
+
+    def stage_times(self) -> list:
+        """Kernel durations (ms) of the last spoly_solve_1bounce call made with
+        SPOLY_FLAG_STAGE_TIMES (waits for it)."""
+        buf = (ctypes.c_float * 8)()
+        n = load_library().spoly_stage_times(self.h, buf, 8)
+        if n < 0:
+            raise SpolyError("spoly_stage_times failed")
+        return [float(buf[i]) for i in range(n)]
 
     # ---------------------------------------------------------------- solve
     def solve_1bounce(self, mesh: DeviceMesh, x0s: DevicePoints, x2s: DevicePoints, q_x0: torch.Tensor,
