@@ -29,7 +29,9 @@ PEAK_FP32 = 157.3   # TFLOP/s, published FP32 vector peak (packed FP32 instructi
 PEAK_VALU = 78.6    # TFLOP/s: 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, fp32 (non-packed) and fp64
 PEAK_BF16 = 2500.0  # TFLOP/s, dense bf16 matrix cores
 PEAK_HBM = 8000.0   # GB/s
-VALU_ISSUE = 256 * 4 * 2.4e9 / 4   # wave64 VALU instructions per second (16-lane SIMDs, 4 per CU)
+# wave64 VALU instructions per second if every SIMD (16 lanes, 4 per CU) issues one every 4 cycles; the
+# glints front kernel counts 13% more than this (profiles/valu_counters.md), so it is a scale, not a bound
+VALU_ISSUE = 256 * 4 * 2.4e9 / 4
 
 # Algorithmic operations per instance by stage (coefficients, elimination, root finding in v, path phase),
 # from the oracle's op counter over seeded samples of each workload: profiles/algorithmic_flops.md, written
@@ -46,10 +48,15 @@ PRUNER_FLOP = 2 * (42 * 128 + 2 * 128 * 128 + 128)   # multiply-adds of the four
 # FETCH_SIZE and WRITE_SIZE (KiB per dispatch), scaled by what the same counters read for a plain 256 MiB
 # device copy.  Valid only for the kernel sources they were taken on (sha256 prefix over _KERNEL_SOURCES,
 # the cull included: it sets the order of the candidates); otherwise traffic is null.
-TRAFFIC_FRONT = None
-# VALU wave-instructions per launch (rocprofv3 --pmc SQ_INSTS_VALU) of each kernel on its workload, under the
-# same source check.
-VALU_INSTS = None
+TRAFFIC_FRONT = {"sha": "0a935f5b0a43f05d", "candidates": 99118956, "fetch_kib": 680467.2, "write_kib": 1900542.1,
+                 "fetch_scale": 262144.0 / 131083.5, "write_scale": 262144.0 / 262144.0}
+# VALU wave-instructions (rocprofv3 --pmc SQ_INSTS_VALU) per launch of each one-vertex kernel on the glints
+# workload, and per tuple of the two-vertex solve on the RR and TT legs, under the same source check
+# (profiles/valu_counters.md).
+VALU_INSTS = {"sha": "0a935f5b0a43f05d",
+              "k_ob_front_R": 2.917e9, "k_ob_back_R": 5.977e8, "k_ob_full_R": 4.107e7,
+              "k_ob_coef_T": 6.219e8, "k_ob_iso_T": 1.690e8, "k_ob_back_T": 1.497e8,
+              "k_tt_solve_RR_per_tuple": 1.438e12 / 9256723, "k_tt_solve_TT_per_tuple": 1.976e12 / 6477601}
 _KERNEL_SOURCES = ("onebounce.hip", "spoly_dev.hpp", "laplace_gen.inc", "onebounce.hpp", "cull.hip",
                    "twobounce.hip", "twobounce.hpp", "pruner.hip")
 
@@ -74,11 +81,17 @@ def traffic_bytes(candidates: int):
     return per * candidates
 
 
-def valu_insts(kernel: str):
+def valu_insts(kernel: str, instances: int | None = None):
+    """VALU wave-instructions of one launch (per-instance figures scaled by
+    `instances`), or None if the kernels changed since they were counted."""
     t = VALU_INSTS
-    if t is None or _kernel_sha() != t["sha"] or kernel not in t:
+    if t is None or _kernel_sha() != t["sha"]:
         return None
-    return t[kernel]
+    if kernel in t:
+        return t[kernel]
+    if instances is not None and kernel + "_per_tuple" in t:
+        return t[kernel + "_per_tuple"] * instances
+    return None
 
 
 def kernel_obj(name, flop, ms, peak, dtype, insts=None, **extra):
@@ -87,6 +100,8 @@ def kernel_obj(name, flop, ms, peak, dtype, insts=None, **extra):
     o = {"kernel": name, "dtype": dtype, "bound": "alu", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
          "frac": ach / peak, "ms": ms, "algorithmic_flop": flop}
     if insts is not None:
+        o["valu_insts"] = insts
+        o["valu_insts_per_s"] = insts / (ms * 1e-3)
         o["valu_issue_frac"] = insts / (ms * 1e-3) / VALU_ISSUE
     o.update(extra)
     return o
@@ -102,8 +117,9 @@ def main():
     ap.add_argument("--res", type=int, default=256, help="shading points per side")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
-    ap.add_argument("--legs", default="glints,rr,mixed,caustic",
+    ap.add_argument("--legs", default="glints,rr,completeness,mixed,caustic",
                     help="comma list: glints (the headline line), rr (two reflections between two wavy mirrors), "
+                         "completeness (two-vertex paths found at 10/100/1000/4095 pieces), "
                          "mixed (2M-instance persistent launch), "
                          "caustic (learned pruner against the exhaustive two-vertex solve)")
     ap.add_argument("--mixed-total", type=int, default=2_000_000)
@@ -280,6 +296,8 @@ def main():
     ctx = spoly.Context(0)
     if "rr" in legs:
         out["two_reflections"] = rr_leg(args, ctx)
+    if "completeness" in legs:
+        out["solver_completeness"] = completeness_leg(args, ctx)
     if "mixed" in legs:
         out["mixed"] = mixed_leg(args, ctx)
     if "caustic" in legs:
@@ -408,8 +426,58 @@ def rr_leg(args, ctx):
             "valid_paths_per_s": paths / med * 1e3, "us_per_tuple": med * 1e3 / n,
             "paper_context": "Table 3, RR (bisection solver, RTX 4080, its own two-dragon scene): 4.936 us per "
                              "triangle pair",
-            "roofline": kernel_obj("k_tt_solve (RR)", sum(ops) * n, med, PEAK_VALU, "f64", valu_insts("k_tt_solve_RR"),
-                                   flop_per_instance=sum(ops))}
+            "roofline": kernel_obj("k_tt_solve (RR)", sum(ops) * n, med, PEAK_VALU, "f64",
+                                   valu_insts("k_tt_solve_RR", n), flop_per_instance=sum(ops))}
+
+
+def completeness_leg(args, ctx):
+    """Solver completeness (Sec. 6, validation of the bisection solver): the
+    same two-vertex tuples solved with 10, 100, 1000 and 4095 pieces of the
+    sign scan (10 bisection steps each); the paths each resolution finds
+    against the finest one, and the time each takes."""
+    import torch
+    from paper_2405_13409_amd import scenes, spoly
+
+    sets = []
+    sph = scenes.caustic_sphere()
+    x3 = scenes.CAUSTIC_LIGHT_OUTSIDE
+    rec, ex, en = scenes.caustic_traced(8, 0.35)
+    Q = [np.column_stack([np.full(len(t), k), t]) for k, t in
+         enumerate(scenes.tuples_near(sph, rec[k], x3[0], ex[k], en[k], 0.1) for k in range(len(rec)))]
+    Q = np.concatenate(Q)
+    sets.append(("caustic TT: 64 receivers where traced caustic paths land, tuples within 0.1 of the path",
+                 "TT", sph, rec, x3, Q[:, 0], np.zeros(len(Q)), Q[:, 1:], (1.0, 1.5, 1.0)))
+    gap = scenes.mirror_gap()
+    rr = scenes.points_grid(4, -0.6, 0.6, 0.5)
+    dm = spoly.DeviceMesh(gap.P, gap.N, gap.tri)
+    q0, q3, qt = ctx.cull_2bounce(dm, spoly.DevicePoints(rr), spoly.DevicePoints(scenes.MIRROR_GAP_LIGHT),
+                                  (1.0, 1.0, 1.0), 1e-3)
+    sets.append(("mirror gap RR: 16 receivers (4x4 grid), every cone-culled tuple", "RR", gap, rr,
+                 scenes.MIRROR_GAP_LIGHT, q0.cpu().numpy(), q3.cpu().numpy(), qt.cpu().numpy().reshape(-1, 2),
+                 (1.0, 1.0, 1.0)))
+    out = {}
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).cuda()  # noqa: E731
+    for name, chain, mesh, x0, x3_, j0, j3, tt, eta in sets:
+        dm = spoly.DeviceMesh(mesh.P, mesh.N, mesh.tri)
+        d0, d3 = spoly.DevicePoints(x0), spoly.DevicePoints(x3_)
+        a0, a3, at = dev(j0), dev(j3), dev(tt)
+        res, ref = {}, None
+        for pieces in (4095, 1000, 100, 10):
+            prm = spoly.tt_default_params()
+            prm.pieces = pieces
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            s = ctx.solve_2bounce(dm, d0, d3, a0, a3, at, eta, params=prm, chain=chain)
+            b.record()
+            b.synchronize()
+            key = {(int(r["query"]), round(float(r["u"][0]), 7), round(float(r["v"][0]), 7)) for r in s}
+            if ref is None:
+                ref = key
+            res[str(pieces)] = {"paths": len(key), "missed_vs_4095": len(ref - key),
+                                "not_in_4095": len(key - ref), "ms": a.elapsed_time(b)}
+        out[chain] = {"workload": name, "tuples": len(j0), "by_pieces": res}
+    return out
 
 
 def caustic_leg(args, ctx):
@@ -439,7 +507,7 @@ def caustic_leg(args, ctx):
     ops = OPS["caustic_TT"]
     r["kernels"] = [
         kernel_obj("k_tt_solve (TT, exhaustive)", sum(ops) * r["n_tuples"], r["ms_exhaustive"], PEAK_VALU, "f64",
-                   valu_insts("k_tt_solve_TT"), flop_per_instance=sum(ops)),
+                   valu_insts("k_tt_solve_TT", r["n_tuples"]), flop_per_instance=sum(ops)),
         dict(kernel_obj("pruner scoring (feature gather + 4 dense layers)", PRUNER_FLOP * r["n_tuples"],
                         r["ms_score"], PEAK_BF16, "bf16"), bound="mfma", flop_per_instance=PRUNER_FLOP),
     ]

@@ -68,7 +68,10 @@ class PruneReport:
 
     def as_dict(self) -> dict:
         d = dataclasses.asdict(self)
-        d.update(ms_pruned=self.ms_pruned, recall=self.recall, path_recall=self.path_recall, speedup=self.speedup)
+        d.update(ms_pruned=self.ms_pruned, recall=self.recall, path_recall=self.path_recall, speedup=self.speedup,
+                 recall_lower_95=recall_lower_bound(self.kept_positives, self.positives))
+        if getattr(self, "sweep", None) is not None:
+            d["threshold_sweep"] = self.sweep
         return d
 
 
@@ -125,4 +128,41 @@ def prune_vs_exhaustive(ctx, dm, d0, d3, T: pr.Tuples, net: pr.Pruner, reps: int
     n_pr = int(cnt.item())
     kept = np.zeros(n, dtype=bool)
     kept[kidx.cpu().numpy()] = True
-    return PruneReport(n, nk, int(lab.sum()), int((lab & kept).sum()), n_ex, n_pr, ms_ex, ms_sc, ms_kept)
+    rep = PruneReport(n, nk, int(lab.sum()), int((lab & kept).sum()), n_ex, n_pr, ms_ex, ms_sc, ms_kept)
+    rep.sweep = threshold_sweep(ctx, dm, d0, d3, T, net, lab, out, cnt, eta)
+    return rep
+
+
+def recall_lower_bound(k: int, n: int, conf: float = 0.95) -> float:
+    """One-sided Clopper-Pearson lower confidence bound on a recall of k/n."""
+    if n == 0:
+        return 1.0
+    if k == 0:
+        return 0.0
+    from scipy.stats import beta
+
+    return float(beta.ppf(1.0 - conf, k, n - k + 1))
+
+
+def threshold_sweep(ctx, dm, d0, d3, T: pr.Tuples, net: pr.Pruner, lab: np.ndarray, out, cnt, eta=ETA,
+                    factors=(1.0, 0.1, 0.01)):
+    """Recall, kept fraction and pruned time at the calibrated threshold times
+    each factor (scores from one scoring pass; the kept tuples solved and timed)."""
+    n = T.n
+    scores = torch.empty(max(n, 1), dtype=torch.float32, device="cuda")
+    keep = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+    kc = torch.zeros(1, dtype=torch.int64, device="cuda")
+    ctx.prune_score(dm, d0, d3, T.q0, T.q3, T.qt, net.params, net.threshold, scores=scores, keep=keep, keep_count=kc)
+    sc = scores[:n].cpu().numpy()
+    rows = []
+    for f in factors:
+        th = net.threshold * f
+        kept = sc >= th
+        K = T.take(torch.from_numpy(np.nonzero(kept)[0]).cuda())
+        ms = _timed(lambda: solve_count(ctx, dm, d0, d3, K, out, cnt, eta), 3)
+        kp = int((lab & kept).sum())
+        rows.append({"threshold": th, "kept": int(kept.sum()), "kept_fraction": float(kept.mean()) if n else 0.0,
+                     "positives": int(lab.sum()), "kept_positives": kp,
+                     "recall": kp / int(lab.sum()) if lab.sum() else 1.0,
+                     "recall_lower_95": recall_lower_bound(kp, int(lab.sum())), "ms_solve_kept": ms})
+    return rows

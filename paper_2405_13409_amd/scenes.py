@@ -235,6 +235,50 @@ def caustic_sphere() -> Mesh:
     return Mesh(m.P @ R.T, m.N @ R.T, m.tri)
 
 
+def caustic_traced(n_side: int = 8, span: float = 0.35, radius: float = 0.5, light=None):
+    """Receivers where caustic paths exist: rays from the light aimed at the
+    sphere's centre shifted by offsets on an n_side x n_side grid over
+    [-span, span]^2, refracted into and out of the exact sphere (IOR 1.5)
+    and followed to the receiver plane z = -1.  Returns the receivers [n,3],
+    the exit points (receiver side) and the entry points (light side)."""
+    x3 = (CAUSTIC_LIGHT_OUTSIDE if light is None else np.asarray(light, dtype=np.float64).reshape(1, 3))[0]
+
+    def nz(x):
+        return x / np.linalg.norm(x)
+
+    def refract(d, n, eta):
+        c = -d @ n
+        k = 1.0 - eta * eta * (1.0 - c * c)
+        return eta * d + (eta * c - math.sqrt(k)) * n
+
+    rec, ex, en = [], [], []
+    g = np.linspace(-span, span, n_side)
+    for ox in g:
+        for oy in g:
+            d = nz(np.array([ox, oy, 0.0]) - x3)
+            b = x3 @ d
+            t = -b - math.sqrt(b * b - (x3 @ x3 - radius * radius))
+            p = x3 + t * d
+            d2 = nz(refract(d, nz(p), 1.0 / 1.5))
+            q = p + (-2.0 * (p @ d2)) * d2
+            d3 = nz(refract(d2, -nz(q), 1.5))
+            rec.append(q + ((-1.0 - q[2]) / d3[2]) * d3)
+            ex.append(q)
+            en.append(p)
+    return np.asarray(rec), np.asarray(ex), np.asarray(en)
+
+
+def tuples_near(mesh: Mesh, x0, x3, p1, p2, r: float) -> np.ndarray:
+    """(T1, T2) pairs with T1's centroid within r of p1 and facing x0, and
+    T2's within r of p2 and facing x3 (by the mean vertex normal)."""
+    c = mesh.P[mesh.tri].mean(1)
+    nc = mesh.N[mesh.tri].mean(1)
+    t1 = np.nonzero((((x0 - c) * nc).sum(1) > 0) & (np.linalg.norm(c - p1, axis=1) < r))[0]
+    t2 = np.nonzero((((x3 - c) * nc).sum(1) > 0) & (np.linalg.norm(c - p2, axis=1) < r))[0]
+    A, B = np.meshgrid(t1, t2, indexing="ij")
+    return np.stack([A.ravel(), B.ravel()], 1).astype(np.int32)
+
+
 def caustic_receivers(res: int = 64) -> np.ndarray:
     """res x res cell-centre receivers on [-2,2]^2 at z = -1."""
     return points_grid(res, -2.0, 2.0, -1.0)
