@@ -1,4 +1,4 @@
-"""ctypes wrapper of the FP64 CPU oracle (spoly_oracle.c).
+"""ctypes wrapper of the FP64 CPU oracle (spoly_oracle.c, tail_oracle.c).
 
 TEST INFRASTRUCTURE: only the test-suite, the smoke check and the CPU-baseline
 leg of the benchmark import this module.  It takes plain numpy arrays; it does
@@ -13,7 +13,7 @@ import subprocess
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "spoly_oracle.c")
+SRCS = [os.path.join(HERE, "spoly_oracle.c"), os.path.join(HERE, "tail_oracle.c")]
 LIB = os.path.join(HERE, "liboracle.so")
 
 SOL_DTYPE = np.dtype([("query", np.int32), ("flags", np.int32), ("u1", np.float64), ("v1", np.float64),
@@ -44,9 +44,9 @@ def default_params(two_bounce: bool = False) -> Params:
 
 
 def build(force: bool = False) -> str:
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < max(os.path.getmtime(s) for s in SRCS):
         tmp = LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-o", tmp, SRC, "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-o", tmp, *SRCS, "-lm"])
         os.replace(tmp, LIB)
     return LIB
 
@@ -83,6 +83,11 @@ def lib():
                                  ctypes.c_double, P]
         L.or_cull_1bounce.argtypes = [P, P, P, ctypes.c_int64, P, ctypes.c_int64, P, ctypes.c_int64,
                                       ctypes.c_double, ctypes.c_double, ctypes.c_double, P]
+        L.ot_tail.argtypes = [P, P, P, ctypes.c_int64, P, P, P, P, P, P, P, ctypes.c_int64, ctypes.c_int32, P, P,
+                              ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, P, P, P, P, P]
+        L.ot_seg_tri.argtypes = [P, P, P, P, P, ctypes.c_int64, ctypes.c_double, P, P]
+        L.ot_fresnel_t.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        L.ot_fresnel_t.restype = ctypes.c_double
         _lib = L
     return _lib
 
@@ -349,3 +354,51 @@ def cull_tt(P, N, tri, x0s, x3s, eta=(1.0, 1.5, 1.0), margin=0.0) -> np.ndarray:
     keep = np.zeros(n0 * n3 * nt * nt, dtype=np.uint8)
     L.or_cull_tt(_p(P), _p(N), _p(tri), nt, _p(x0s), n0, _p(x3s), n3, _p(eta), margin, _p(keep))
     return keep.reshape(n0, n3, nt, nt).astype(bool)
+
+
+# ------------------------------------------------------------------ path-phase tail (tail_oracle.c)
+
+TAIL_DTYPE = np.dtype([("mask", np.int32), ("margin", np.float64), ("fresnel", np.float64), ("E", np.float64),
+                       ("E_change", np.float64)])
+
+
+def tail(P, N, tri, x0s, xls, q_x0, q_xl, ptri, pu, pv, chain: str, eta, intensity=1.0, rho=1.0, teps=1e-6,
+         h=1e-5) -> np.ndarray:
+    """Visibility and contribution of n paths with k = len(chain) vertices.
+    ptri, pu, pv: [n, k] triangle ids and barycentrics of x1..xk; q_x0, q_xl:
+    receiver and light index per path; eta: k+1 indices (eta[i] between x_i
+    and x_{i+1}).  Returns a TAIL_DTYPE record per path."""
+    L = lib()
+    k = len(chain)
+    assert k in (1, 2) and set(chain) <= {"R", "T"} and len(eta) == k + 1
+    P, N, x0s, xls = (_c(a, np.float64) for a in (P, N, x0s, xls))
+    tri, q_x0, q_xl = (_c(a, np.int32) for a in (tri, q_x0, q_xl))
+    ptri = _c(np.asarray(ptri).reshape(-1, k), np.int32)
+    pu = _c(np.asarray(pu).reshape(-1, k), np.float64)
+    pv = _c(np.asarray(pv).reshape(-1, k), np.float64)
+    n = len(ptri)
+    ev = np.array([0 if c == "R" else 1 for c in chain], dtype=np.int32)
+    eta = _c(eta, np.float64)
+    out = {f: np.zeros(n, dtype=TAIL_DTYPE[f]) for f in TAIL_DTYPE.names}
+    L.ot_tail(_p(P), _p(N), _p(tri), len(tri), _p(x0s), _p(xls), _p(q_x0), _p(q_xl), _p(ptri), _p(pu), _p(pv), n,
+              k, _p(ev), _p(eta), float(intensity), float(rho), float(teps), float(h),
+              *(_p(out[f]) for f in TAIL_DTYPE.names))
+    rec = np.zeros(n, dtype=TAIL_DTYPE)
+    for f in TAIL_DTYPE.names:
+        rec[f] = out[f]
+    return rec
+
+
+def seg_tri(p, q, a, b, c, teps=0.0):
+    """Moller-Trumbore segment/triangle test per row; returns (hit, margin)."""
+    L = lib()
+    p, q, a, b, c = (_c(np.asarray(x).reshape(-1, 3), np.float64) for x in (p, q, a, b, c))
+    n = len(p)
+    hit = np.zeros(n, dtype=np.int32)
+    margin = np.zeros(n)
+    L.ot_seg_tri(_p(p), _p(q), _p(a), _p(b), _p(c), n, float(teps), _p(hit), _p(margin))
+    return hit.astype(bool), margin
+
+
+def fresnel_t(n1: float, n2: float, ci: float) -> float:
+    return float(lib().ot_fresnel_t(float(n1), float(n2), float(ci)))
