@@ -117,8 +117,9 @@ def main():
     ap.add_argument("--res", type=int, default=256, help="shading points per side")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
-    ap.add_argument("--legs", default="glints,rr,completeness,mixed,caustic",
-                    help="comma list: glints (the headline line), rr (two reflections between two wavy mirrors), "
+    ap.add_argument("--legs", default="glints,tail,rr,completeness,mixed,caustic",
+                    help="comma list: glints (the headline line), tail (visibility + contribution of the headline "
+                         "step's paths), rr (two reflections between two wavy mirrors), "
                          "completeness (two-vertex paths found at 10/100/1000/4095 pieces), "
                          "mixed (2M-instance persistent launch), "
                          "caustic (learned pruner against the exhaustive two-vertex solve)")
@@ -291,6 +292,9 @@ def main():
         "roofline": roofline,
         "kernels": kernels,
     }
+    tail_sample = None
+    if "tail" in legs:
+        out["path_tail"], tail_sample = tail_leg(ctxs["R"], spoly, dm, pts, dl, buf)
     for ev in ctxs:
         ctxs[ev].close()
     ctx = spoly.Context(0)
@@ -304,8 +308,108 @@ def main():
         out["pruned_vs_exhaustive"] = caustic_leg(args, ctx)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args, mesh, light, ctx)
+        if tail_sample is not None:
+            out["cpu_baseline"]["path_tail"] = cpu_tail_baseline(mesh, light, tail_sample)
     print(json.dumps(out), flush=True)
     ctx.close()
+
+
+TAIL_BYTES = 56 + 8 + 4 + 8 + 8  # per path: record, two query ids, mask, contribution, image add
+
+
+def tail_leg(ctx, spoly, dm, pts, dl, buf, reps: int = 5):
+    """Visibility (device BVH) and contribution of every valid path of the
+    last headline step, R and T, straight from the solve's output buffer and
+    device count; the receivers' image accumulated with the z-facing plane
+    weight.  Returns the leg's record and a host sample for the oracle."""
+    import torch
+
+    t0 = time.perf_counter()
+    bvh = spoly.Bvh(ctx, dm)
+    build_ms = (time.perf_counter() - t0) * 1e3
+    res = {"bvh_build_ms": build_ms, "bvh_triangles": dm.n_tris}
+    stream = torch.cuda.current_stream()
+    sample = {}
+    tot_paths, tot_ms = 0, 0.0
+    for ev, eta in (("R", (1.0, 1.0)), ("T", (1.5, 1.0))):
+        b = buf[ev]
+        n = int(b["scount"].item())
+        mask = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+        contrib = torch.empty(max(n, 1), dtype=torch.float64, device="cuda")
+        img = torch.zeros(pts[ev].n, dtype=torch.float64, device="cuda")
+        prm = spoly.tail_default_params(rcv_normal=(0.0, 0.0, 1.0))
+
+        def run():
+            ctx.path_tail(dm, bvh, ev, eta, pts[ev], dl, b["q0"], b["q2"], b["out"], n_sols=n, sol_count=b["scount"],
+                          params=prm, mask=mask, contrib=contrib, image=img)
+
+        run()
+        ms = []
+        for _ in range(reps):
+            img.zero_()
+            e_a = torch.cuda.Event(enable_timing=True)
+            e_b = torch.cuda.Event(enable_timing=True)
+            e_a.record(stream)
+            run()
+            e_b.record(stream)
+            e_b.synchronize()
+            ms.append(e_a.elapsed_time(e_b))
+        m = float(np.mean(ms))
+        mk = mask[:n].cpu().numpy()
+        gbps = n * TAIL_BYTES / (m * 1e-3) / 1e9
+        res[ev] = {"paths": n, "ms": m, "paths_per_s": n / (m * 1e-3), "blocked_fraction": float((mk != 0).mean()),
+                   "singular": int(((mk & spoly.TAIL_SINGULAR) != 0).sum()),
+                   "image_total": float(img.sum().item()),
+                   "kernel": f"k_tail<1> ({ev})",
+                   "roofline": {"bound": "hbm", "achieved": gbps, "peak": PEAK_HBM, "unit": "GB/s",
+                                "frac": gbps / PEAK_HBM, "algorithmic_bytes_per_path": TAIL_BYTES,
+                                "note": "the BVH, mesh and endpoints stay in L2/MALL; the kernel is bound by "
+                                        "dependent node loads of the traversal, not by HBM"}}
+        tot_paths += n
+        tot_ms += m
+        k = min(n, 600)
+        recs = b["out"][: k * spoly.SOLUTION_DTYPE.itemsize].cpu().numpy().view(spoly.SOLUTION_DTYPE)
+        q = recs["query"]
+        sample[ev] = dict(recs=recs, x0=pts[ev], q0=b["q0"][: int(q.max()) + 1].cpu().numpy() if k else None,
+                          q2=b["q2"][: int(q.max()) + 1].cpu().numpy() if k else None, eta=eta,
+                          mask=mk[:k], contrib=contrib[:k].cpu().numpy())
+    res["paths_per_s"] = tot_paths / (tot_ms * 1e-3)
+    res["workload"] = "every valid path of one headline step (R and T lists as the solve wrote them)"
+    bvh.close()
+    return res, sample
+
+
+def cpu_tail_baseline(mesh, light, sample):
+    """The tail oracle (every segment against every triangle; contribution by
+    differences of a forward trace) on one core over the first paths of each
+    list, and the GPU's agreement with it on those paths."""
+    sys.path.insert(0, os.path.join(ROOT, "oracle"))
+    import oracle
+
+    threads = oracle.set_threads(1)
+    out, n_all, t_all = {}, 0, 0.0
+    for ev, s in sample.items():
+        recs = s["recs"]
+        if len(recs) == 0:
+            continue
+        x0 = np.column_stack([c.cpu().numpy() for c in s["x0"].cols])
+        q = recs["query"]
+        t0 = time.perf_counter()
+        ot = oracle.tail(mesh.P, mesh.N, mesh.tri, x0, light, s["q0"][q], s["q2"][q], recs["tri"][:, :1],
+                         recs["u"][:, :1], recs["v"][:, :1], ev, s["eta"])
+        dt = time.perf_counter() - t0
+        n_all += len(recs)
+        t_all += dt
+        ok = ot["margin"] > 1e-9
+        st = ok & (ot["E_change"] < 1e-7) & (ot["E"] > 0)
+        rel = np.abs(s["contrib"][st] - ot["E"][st]) / ot["E"][st]
+        out[ev] = {"paths": int(len(recs)), "mask_compared": int(ok.sum()),
+                   "mask_mismatches": int(((s["mask"][ok] & 3) != ot["mask"][ok]).sum()),
+                   "contrib_compared": int(st.sum()), "contrib_max_rel_err": float(rel.max()) if len(rel) else None}
+    oracle.set_threads(threads)
+    return {"value": n_all / t_all if t_all else None, "unit": "paths/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {n_all} paths of the headline step's R and T lists, brute-force visibility over "
+                      f"{mesh.nt} triangles per segment", "gpu_agreement": out}
 
 
 def copy_calibration(nbytes: int = 256 << 20, reps: int = 5):

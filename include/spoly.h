@@ -340,6 +340,71 @@ spoly_status spoly_solve_mixed(spoly_ctx *ctx,
                                spoly_solution *out, int64_t out_capacity, unsigned long long *out_count,
                                void *stream);
 
+/*
+ * Path-phase tail (Sec. 5.3, "The whole pipeline"): after the path-space
+ * check a chain is dropped when the segment from any of its vertices to the
+ * next (x0 -> x1 -> ... -> x_k -> light) is blocked by the mesh; every chain
+ * that stays contributes to its endpoint x0, and several chains between the
+ * same endpoints add up.
+ *
+ * spoly_bvh_build: bounding volume hierarchy over the mesh's triangles (a
+ * linear hierarchy over Morton-sorted centroids), built on ctx's device on
+ * `stream` and waited for.  Allocates device memory owned by *out until
+ * spoly_bvh_destroy (NULL is ignored).  The mesh arrays must not change
+ * while the hierarchy is in use.  E_INVALID_ARG on a bad mesh, E_DEVICE on a
+ * HIP error (nothing is left allocated).
+ */
+typedef struct spoly_bvh spoly_bvh;
+spoly_status spoly_bvh_build(spoly_ctx *ctx, const spoly_mesh *mesh, spoly_bvh **out, void *stream);
+void spoly_bvh_destroy(spoly_bvh *bvh);
+
+/* Tail parameters [host]; spoly_tail_default_params fills I = 1, rho = 1,
+ * t_eps = 1e-6 and a zero receiver normal. */
+typedef struct {
+    double intensity;      /* radiant intensity of the isotropic point light at x_{k+1}       */
+    double reflectance;    /* rho, the factor of every reflection vertex                       */
+    double t_eps;          /* hits within t_eps (segment parameter) of either end do not block */
+    double rcv_normal[3];  /* image weight |w0 . n| (w0 the unit direction x0 -> x1); all      */
+                           /* zero: weight 1 (irradiance on the plane normal to the ray)       */
+} spoly_tail_params;
+void spoly_tail_default_params(spoly_tail_params *p);
+
+/*
+ * Visibility and contribution of validated chains (records `sols` from
+ * spoly_solve_1bounce (k = 1) or spoly_solve_nbounce (k = 2) over the same
+ * query arrays q_x0 / q_xl and endpoint sets; device memory).  chain [host, k]
+ * and eta [host, k+1] as for the solve (eta[i] the index between x_i and
+ * x_{i+1}; a reflection needs equal indices on both sides).  Per record p:
+ *  mask[p]    (device int32, optional): bit i set when x_i -> x_{i+1} is
+ *             blocked: some triangle other than those carrying its two ends
+ *             meets it at closed barycentrics and a segment parameter in
+ *             [t_eps, 1 - t_eps] (double-precision Moller-Trumbore);
+ *             bit 30 set when the constraint Jacobian is singular (a caustic
+ *             point: contribution undefined, reported as 0); bit 29 set if a
+ *             traversal hit its stack or visit bound (not reachable for a
+ *             hierarchy from spoly_bvh_build);
+ *  contrib[p] (device double, optional): E = I * prod F_i * dw/dA, the
+ *             irradiance at x0 on the plane normal to the arriving ray, before
+ *             visibility; F_i is the unpolarised Fresnel transmittance at a
+ *             refraction (interpolated shading normal) and rho at a
+ *             reflection; dw/dA the light's solid angle per unit of that area,
+ *             by implicit differentiation of the vertex constraints of Eq. eq_ch;
+ *  image[q_x0[query]] (device double [x0s->n], optional): += E * weight
+ *             (rcv_normal) for each record with mask 0, by atomic adds (the
+ *             caller zeroes it; the order of the adds is unspecified).
+ * sol_count (device, optional): only min(*sol_count, n_sols) records are read,
+ * so a solve's out_count can be passed without a host round trip.  Asynchronous
+ * on `stream`.  E_INVALID_ARG on bad arguments or a hierarchy of another mesh
+ * or device; E_UNSUPPORTED for k outside 1..2.
+ */
+spoly_status spoly_path_tail(spoly_ctx *ctx, const spoly_mesh *mesh, const spoly_bvh *bvh, int32_t k,
+                             const spoly_event *chain, const double *eta,
+                             const spoly_points *x0s, const spoly_points *xls,
+                             const int32_t *q_x0, const int32_t *q_xl,
+                             const spoly_solution *sols, int64_t n_sols, const unsigned long long *sol_count,
+                             const spoly_tail_params *params, int32_t *mask, double *contrib, double *image,
+                             void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -2,6 +2,7 @@
 // context (device buffers it owns) and kernel launches.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
@@ -12,6 +13,7 @@
 #include "sqrt_table.inc"
 #include "pruner.hpp"
 #include "mixed.hpp"
+#include "tail.hpp"
 
 struct spoly_ctx {
     int device;
@@ -650,3 +652,93 @@ extern "C" spoly_status spoly_solve_mixed(spoly_ctx* ctx, const spoly_mesh* mesh
     return dev_err(spoly::launch_mixed(M, int(ev1), int(prec), cus * shape->workgroups_per_cu,
                                        static_cast<hipStream_t>(stream)));
 }
+
+// ------------------------------------------------------------------ path-phase tail
+
+struct spoly_bvh {
+    int device;
+    spoly::BvhStore store;
+};
+
+extern "C" {
+
+spoly_status spoly_bvh_build(spoly_ctx* ctx, const spoly_mesh* mesh, spoly_bvh** out, void* stream)
+{
+    if (!ctx || !mesh_ok(mesh) || !out) return SPOLY_E_INVALID_ARG;
+    *out = nullptr;
+    if (hipSetDevice(ctx->device) != hipSuccess) return SPOLY_E_DEVICE;
+    spoly_bvh* b = static_cast<spoly_bvh*>(std::calloc(1, sizeof(spoly_bvh)));
+    if (!b) return SPOLY_E_DEVICE;
+    b->device = ctx->device;
+    if (spoly::bvh_build(mesh->px, mesh->py, mesh->pz, mesh->tri, mesh->n_tris, &b->store,
+                         static_cast<hipStream_t>(stream)) != hipSuccess) {
+        std::free(b);
+        return SPOLY_E_DEVICE;
+    }
+    *out = b;
+    return SPOLY_OK;
+}
+
+void spoly_bvh_destroy(spoly_bvh* bvh)
+{
+    if (!bvh) return;
+    (void)hipSetDevice(bvh->device);
+    spoly::bvh_free(&bvh->store);
+    std::free(bvh);
+}
+
+void spoly_tail_default_params(spoly_tail_params* p)
+{
+    if (!p) return;
+    p->intensity = 1.0;
+    p->reflectance = 1.0;
+    p->t_eps = 1e-6;
+    p->rcv_normal[0] = p->rcv_normal[1] = p->rcv_normal[2] = 0.0;
+}
+
+spoly_status spoly_path_tail(spoly_ctx* ctx, const spoly_mesh* mesh, const spoly_bvh* bvh, int32_t k,
+                             const spoly_event* chain, const double* eta, const spoly_points* x0s,
+                             const spoly_points* xls, const int32_t* q_x0, const int32_t* q_xl,
+                             const spoly_solution* sols, int64_t n_sols, const unsigned long long* sol_count,
+                             const spoly_tail_params* params, int32_t* mask, double* contrib, double* image,
+                             void* stream)
+{
+    if (!ctx || !mesh_ok(mesh) || !bvh || !chain || !eta || !pts_ok(x0s) || !pts_ok(xls) || !params)
+        return SPOLY_E_INVALID_ARG;
+    if (k < 1 || k > 2) return SPOLY_E_UNSUPPORTED;
+    if (bvh->device != ctx->device || bvh->store.n_tris != mesh->n_tris) return SPOLY_E_INVALID_ARG;
+    if (n_sols < 0 || (n_sols > 0 && (!sols || !q_x0 || !q_xl))) return SPOLY_E_INVALID_ARG;
+    for (int i = 0; i < k; ++i) {
+        if (chain[i] != SPOLY_R && chain[i] != SPOLY_T) return SPOLY_E_INVALID_ARG;
+        if (chain[i] == SPOLY_R && eta[i] != eta[i + 1]) return SPOLY_E_INVALID_ARG;
+    }
+    for (int i = 0; i <= k; ++i)
+        if (!(eta[i] > 0.0)) return SPOLY_E_INVALID_ARG;
+    if (!(params->intensity >= 0.0) || !(params->reflectance >= 0.0) || !(params->t_eps >= 0.0) ||
+        !(params->t_eps < 0.5))
+        return SPOLY_E_INVALID_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess) return SPOLY_E_DEVICE;
+    spoly::TailArgs A;
+    A.bvh.nodes = bvh->store.nodes;
+    A.bvh.tris = bvh->store.tris;
+    A.bvh.n_tris = bvh->store.n_tris;
+    A.px = mesh->px; A.py = mesh->py; A.pz = mesh->pz;
+    A.nx = mesh->nx; A.ny = mesh->ny; A.nz = mesh->nz;
+    A.tri = mesh->tri;
+    A.x0x = x0s->x; A.x0y = x0s->y; A.x0z = x0s->z;
+    A.xlx = xls->x; A.xly = xls->y; A.xlz = xls->z;
+    A.q_x0 = q_x0; A.q_xl = q_xl;
+    A.sols = sols; A.n = n_sols; A.count = sol_count;
+    A.k = k;
+    A.ev[0] = chain[0]; A.ev[1] = k > 1 ? chain[1] : SPOLY_R;
+    A.eta[0] = eta[0]; A.eta[1] = eta[1]; A.eta[2] = k > 1 ? eta[2] : eta[1];
+    A.intensity = params->intensity; A.rho = params->reflectance; A.teps = params->t_eps;
+    A.use_rn = params->rcv_normal[0] != 0.0 || params->rcv_normal[1] != 0.0 || params->rcv_normal[2] != 0.0;
+    double rl = std::sqrt(params->rcv_normal[0] * params->rcv_normal[0] + params->rcv_normal[1] * params->rcv_normal[1] +
+                          params->rcv_normal[2] * params->rcv_normal[2]);
+    for (int i = 0; i < 3; ++i) A.rn[i] = A.use_rn ? params->rcv_normal[i] / rl : 0.0;
+    A.mask = mask; A.contrib = contrib; A.image = image;
+    return dev_err(spoly::launch_tail(A, static_cast<hipStream_t>(stream)));
+}
+
+}  // extern "C"

@@ -7,3 +7,4 @@
 #include "twobounce.hip"
 #include "pruner.hip"
 #include "mixed.hip"
+#include "tail.hip"

@@ -210,6 +210,34 @@ def glints_large_points(event: str, res: int = 256) -> np.ndarray:
     return points_grid(res, -1.0, 1.0, 2.0 if event == "R" else -2.0, 16 if res % 16 == 0 else 1)
 
 
+def with_occluders(mesh: Mesh, quads) -> Mesh:
+    """The mesh plus axis-aligned horizontal rectangles (x0, x1, y0, y1, z),
+    two triangles each with normal +z, appended after the mesh's own."""
+    P, N, T = [mesh.P], [mesh.N], [mesh.tri]
+    base = len(mesh.P)
+    for k, (xa, xb, ya, yb, z) in enumerate(quads):
+        P.append(np.array([[xa, ya, z], [xb, ya, z], [xb, yb, z], [xa, yb, z]], dtype=np.float64))
+        N.append(np.tile([0.0, 0.0, 1.0], (4, 1)))
+        b = base + 4 * k
+        T.append(np.array([[b, b + 1, b + 2], [b, b + 2, b + 3]], dtype=np.int32))
+    return Mesh(np.vstack(P), np.vstack(N), np.vstack(T).astype(np.int32))
+
+
+# three strips between the small glints heightfield and its shading points
+GLINT_STRIPS = [(-0.9, -0.6, -1.3, 1.3, 0.5), (-0.15, 0.15, -1.3, 1.3, 0.5), (0.5, 0.8, -1.3, 1.3, 0.5)]
+
+
+def shadowed_glints(res: int = 48) -> OneBounceWorkload:
+    """A steep 16x16 heightfield (z = 0.15 * 3 sinusoids, freq 1..4, seed 1)
+    lit from low at (1.5, 0.3, 0.5) with res x res shading points on
+    [-1,1]^2 at z = 0.5: its bumps hide one another from the light and from
+    the shading points.  Reflection; every (point, triangle) pair."""
+    mesh = heightfield(16, 0.15, 3, 1.0, 4.0, 1)
+    x0 = points_grid(res, -1.0, 1.0, 0.5)
+    qp, qt = all_pairs(len(x0), mesh.nt)
+    return OneBounceWorkload(mesh, x0, np.asarray([[1.5, 0.3, 0.5]]), qp, np.zeros_like(qp), qt, "R", 1.0, 1.0)
+
+
 GLINTS_LARGE_LIGHT = np.asarray([[0.0, 0.0, 4.0]])
 
 CAUSTIC_LIGHT_OUTSIDE = np.asarray([[0.1, 0.05, 1.5]])

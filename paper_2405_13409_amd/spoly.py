@@ -27,7 +27,8 @@ assert SOLUTION_DTYPE.itemsize == 56
 EXPORTED = ("spoly_ctx_create", "spoly_ctx_destroy", "spoly_default_params", "spoly_status_str",
             "spoly_cull_1bounce", "spoly_solve_1bounce", "spoly_cull_2bounce", "spoly_solve_nbounce",
             "spoly_prune_score", "spoly_pruner_fwd_bwd", "spoly_pruner_step", "spoly_pruner_features",
-            "spoly_solve_mixed", "spoly_tt_default_params", "spoly_solve_1bounce_noalloc", "spoly_stage_times")
+            "spoly_solve_mixed", "spoly_tt_default_params", "spoly_solve_1bounce_noalloc", "spoly_stage_times",
+            "spoly_bvh_build", "spoly_bvh_destroy", "spoly_tail_default_params", "spoly_path_tail")
 SPOLY_FLAG_FORCE_FP64 = 1 << 1
 SPOLY_FLAG_STAGE_TIMES = 1 << 2
 PRUNER_NPARAMS = 38657
@@ -57,6 +58,13 @@ class Params(ctypes.Structure):
                 ("tau", ctypes.c_double), ("u_margin", ctypes.c_double), ("dedup", ctypes.c_double),
                 ("polish_iters", ctypes.c_int32), ("flags", ctypes.c_uint32)]
 
+
+class TailParams(ctypes.Structure):
+    _fields_ = [("intensity", ctypes.c_double), ("reflectance", ctypes.c_double), ("t_eps", ctypes.c_double),
+                ("rcv_normal", ctypes.c_double * 3)]
+
+
+TAIL_SINGULAR = 1 << 30
 
 _lib = None
 
@@ -112,6 +120,15 @@ def load_library(path: str = LIB_PATH):
     L.spoly_solve_mixed.argtypes = [P, MP, PP, PP, P, P, P, I64, ctypes.c_int, D, D, MP, PP, PP, P, P, P, I64, P,
                                     ctypes.c_int, ctypes.POINTER(Params), ctypes.POINTER(MixedShape), P, P, I64, P, P]
     L.spoly_solve_mixed.restype = ctypes.c_int
+    L.spoly_bvh_build.argtypes = [P, MP, ctypes.POINTER(ctypes.c_void_p), P]
+    L.spoly_bvh_build.restype = ctypes.c_int
+    L.spoly_bvh_destroy.argtypes = [P]
+    L.spoly_bvh_destroy.restype = None
+    L.spoly_tail_default_params.argtypes = [ctypes.POINTER(TailParams)]
+    L.spoly_tail_default_params.restype = None
+    L.spoly_path_tail.argtypes = [P, MP, P, I32, P, P, PP, PP, P, P, P, I64, P, ctypes.POINTER(TailParams), P, P, P,
+                                  P]
+    L.spoly_path_tail.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -384,6 +401,72 @@ def _solve_mixed(self, mesh1, x0s1, x2s1, q1_x0, q1_x2, q1_tri, event, eta0, eta
         cap = n
 
 
+class Bvh:
+    """Device bounding volume hierarchy of a DeviceMesh (spoly_bvh_build)."""
+
+    def __init__(self, ctx: "Context", mesh: DeviceMesh):
+        h = ctypes.c_void_p()
+        _check(load_library().spoly_bvh_build(ctx.h, ctypes.byref(mesh.c), ctypes.byref(h), _stream()),
+               "spoly_bvh_build")
+        self.h = h
+        self.mesh = mesh
+
+    def close(self):
+        if self.h:
+            load_library().spoly_bvh_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def tail_default_params(**kw) -> TailParams:
+    p = TailParams()
+    load_library().spoly_tail_default_params(ctypes.byref(p))
+    for k, v in kw.items():
+        if k == "rcv_normal":
+            p.rcv_normal = (ctypes.c_double * 3)(*v)
+        else:
+            setattr(p, k, v)
+    return p
+
+
+def solutions_to_device(sols: np.ndarray) -> torch.Tensor:
+    """SOLUTION_DTYPE records as a device byte tensor."""
+    b = np.ascontiguousarray(sols, dtype=SOLUTION_DTYPE).view(np.uint8)
+    return torch.from_numpy(b.copy()).cuda()
+
+
+def _path_tail(self, mesh: DeviceMesh, bvh: Bvh, chain: str, eta, x0s: DevicePoints, xls: DevicePoints,
+               q_x0: torch.Tensor, q_xl: torch.Tensor, sols: torch.Tensor, n_sols: int | None = None,
+               sol_count: torch.Tensor | None = None, params: TailParams | None = None, mask=None, contrib=None,
+               image=None):
+    """Visibility mask and contribution of solution records `sols` (device
+    bytes, SOLUTION_DTYPE) of the chain `chain` ("R", "T", "RR", ... "TT").
+    Returns (mask int32, contrib float64, image float64 or None) device tensors
+    (allocated when not given; image is accumulated into when given)."""
+    L = load_library()
+    k = len(chain)
+    if k not in (1, 2) or set(chain) - {"R", "T"}:
+        raise SpolyError(f"chain must be one or two of R/T, got {chain!r}")
+    n = int(n_sols if n_sols is not None else sols.numel() // SOLUTION_DTYPE.itemsize)
+    ch = (ctypes.c_int * k)(*(SPOLY_R if c == "R" else SPOLY_T for c in chain))
+    e = _host_doubles(eta)
+    prm = params or tail_default_params()
+    if mask is None:
+        mask = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+    if contrib is None:
+        contrib = torch.empty(max(n, 1), dtype=torch.float64, device="cuda")
+    _check(L.spoly_path_tail(self.h, ctypes.byref(mesh.c), bvh.h, k, ch, e, ctypes.byref(x0s.c), ctypes.byref(xls.c),
+                             _ptr(q_x0), _ptr(q_xl), _ptr(sols), n, _ptr(sol_count), ctypes.byref(prm), _ptr(mask),
+                             _ptr(contrib), _ptr(image), _stream()), "spoly_path_tail")
+    return mask, contrib, image
+
+
+Context.path_tail = _path_tail
 Context.solve_mixed = _solve_mixed
 Context.pruner_features = _pruner_features
 Context.pruner_fwd_bwd = _pruner_fwd_bwd
