@@ -39,8 +39,11 @@ def default_params(two_bounce: bool = False) -> Params:
     bisection steps (Sec. 5.2); u searched on [-m, 1-v+m] before polish with
     m = 1e-4 (one bounce) or 0.05 (two bounces, whose approximate roots can sit
     up to ~1e-2 away from the exact ones); up to 6 Newton steps; two vertices
-    take the sign of det R(v) from the paired product formula (det_method 2)."""
-    return Params(1e-6, 0.05 if two_bounce else 1e-4, 1e-8, 6, 100, 10, 2 if two_bounce else 0)
+    take the sign of det R(v) from the paired product formula with b evaluated
+    from its defining products and the roots at x2 = infinity left out
+    (det_method 3; 2 is the same on expanded coefficients, 1 the plain
+    product, 0 Gaussian elimination on the Bezout matrix)."""
+    return Params(1e-6, 0.05 if two_bounce else 1e-4, 1e-8, 6, 100, 10, 3 if two_bounce else 0)
 
 
 def build(force: bool = False) -> str:

@@ -68,8 +68,9 @@ typedef struct {
     int32_t bisect_iters;/* bisection steps per sign change (10)                        */
     int32_t det_method;  /* sign of det R(v): 0 Gaussian elimination on the Bezout matrix, */
                          /* 1 product formula over the real roots of a(.,v),             */
-                         /* 2 the same product with near-double root pairs left out      */
-                         /*   (the two-vertex default)                                   */
+                         /* 2 the same product with near-double root pairs left out,     */
+                         /* 3 as 2 with b evaluated from its defining products and the   */
+                         /*   roots where x2 is at infinity left out (the default)       */
 } or_params;
 
 typedef struct {
@@ -1033,6 +1034,124 @@ static int res_sign_paired(arena *A, bp a, int ma, bp b, double v)
     return sign;
 }
 
+/* Per-tuple constants of a two-vertex chain, to evaluate b(u, v) at a point
+ * from the same defining products coeffs_2v expands (the mapped direction
+ * Dt at x1, the homogeneous coordinates (kappa, ut, vt) of x2 on T2's plane,
+ * M2, D2 and the product or square form at x2).                            */
+typedef struct {
+    tri_t T1, T2;
+    v3 x0, x3, ax, edge;
+    double eta1, eta2, etap, S, q0, q1, r0, r1, sg, n2len;
+    int ev1, ev2, f2;
+} chain2v;
+
+static void chain2v_setup(chain2v *C, const tri_t *T1, const tri_t *T2, v3 x0, v3 x3, const double *eta,
+                          int ev1, int ev2, const or_sqrtfit *fit)
+{
+    memset(C, 0, sizeof(*C));
+    C->T1 = *T1; C->T2 = *T2; C->x0 = x0; C->x3 = x3;
+    C->eta1 = eta[1]; C->eta2 = eta[2]; C->ev1 = ev1; C->ev2 = ev2;
+    C->f2 = T2->flat ? 0 : 1;
+    C->etap = eta[0] / eta[1];
+    v3 c1 = tri_x(T1, 1.0 / 3.0, 1.0 / 3.0);
+    if (ev1 != 0) {
+        v3 nc1 = tri_n(T1, 1.0 / 3.0, 1.0 / 3.0);
+        v3 d0c = vsub(c1, x0);
+        C->S = vdot(nc1, nc1) * vdot(d0c, d0c);
+        double dnc = vdot(d0c, nc1);
+        double sc = 1.0 - C->etap * C->etap * (1.0 - dnc * dnc / C->S);
+        int p = 0;
+        for (int k = 1; k < 6; ++k) if (sc >= fit->bp[k]) p = k;
+        C->q0 = fit->c[p][0]; C->q1 = fit->c[p][1]; C->r0 = fit->c[p][2]; C->r1 = fit->c[p][3];
+        C->sg = dnc < 0.0 ? -1.0 : 1.0;
+    }
+    v3 c2 = tri_x(T2, 1.0 / 3.0, 1.0 / 3.0);
+    if (ev2 == 0) C->edge = pick_edge2(c2, c1, x3, T2->e1, T2->e2) ? T2->e2 : T2->e1;
+    else pick_axis(c2, c1, x3, &C->ax);
+    C->n2len = vlen(vcross(T2->e1, T2->e2));
+}
+
+/* b(u, v) from its defining products, and |kappa| / (|Dt| |e1 x e2|) of T2:
+ * the sine of the angle between the mapped ray from x1 and T2's plane (0
+ * when x2 is at infinity).                                                 */
+static double b2v_value(const chain2v *C, double u, double v, double *kratio)
+{
+    OPS(160);
+    const tri_t *T1 = &C->T1, *T2 = &C->T2;
+    v3 x1 = tri_x(T1, u, v), n1 = tri_n(T1, u, v);
+    v3 d0 = vsub(x1, C->x0);
+    double nn = vdot(n1, n1), dn = vdot(d0, n1);
+    v3 Dt;
+    if (C->ev1 == 0) {
+        Dt = vsub(vmul(d0, nn), vmul(n1, 2.0 * dn));
+    } else {
+        double e2p = C->etap * C->etap;
+        double beta = (1.0 - e2p) * nn * vdot(d0, d0) + e2p * dn * dn;
+        double num = C->q1 / C->S * beta + C->q0, den = C->r1 / C->S * beta + C->r0;
+        v3 tang = vsub(vmul(d0, nn), vmul(n1, dn));
+        Dt = vadd(vmul(tang, C->etap * den), vmul(n1, C->sg * sqrt(C->S) * num));
+    }
+    v3 q = vsub(x1, T2->p0);
+    v3 Dxe22 = vcross(Dt, T2->e2);
+    double ut = vdot(Dxe22, q), vt = vdot(vcross(q, T2->e1), Dt), ka = vdot(Dxe22, T2->e1);
+    v3 X2 = vadd(vmul(T2->p0, ka), vadd(vmul(T2->e1, ut), vmul(T2->e2, vt)));
+    v3 M2 = vmul(T2->n0, ka);
+    if (C->f2) M2 = vadd(M2, vadd(vmul(T2->dn1, ut), vmul(T2->dn2, vt)));
+    v3 D2 = vsub(vmul(C->x3, ka), X2);
+    double ld = vlen(Dt) * C->n2len;
+    *kratio = ld > 0.0 ? fabs(ka) / ld : 0.0;
+    if (C->ev2 == 0) {
+        v3 t = vcross(M2, C->edge);
+        return vdot(Dt, M2) * vdot(D2, t) + vdot(Dt, t) * vdot(D2, M2);
+    }
+    double l = vdot(vcross(Dt, M2), C->ax), r = vdot(vcross(D2, M2), C->ax);
+    return C->eta1 * C->eta1 * vdot(D2, D2) * l * l - C->eta2 * C->eta2 * vdot(Dt, Dt) * r * r;
+}
+
+/* Sign of the resultant at v by the product formula over the real roots of
+ * a(., v) (paired as in res_sign_paired), with two readings for the chain:
+ * b at each root is evaluated from its defining products (the expanded
+ * coefficients lose every digit at roots far from the triangle), and roots
+ * where the mapped ray runs within 1e-4 rad of parallel to T2's plane are
+ * left out.  There x2 is at infinity, no path can lie, and kappa divides both
+ * a and b when T2 is flat or its vertex normals are proportional to its
+ * positions (a sphere), which makes the resultant vanish identically and
+ * the sign of such a factor a matter of rounding.                         */
+#define OR_KAPPA_SKIP 1e-4
+static int res_sign_chain(arena *A, bp a, int ma, const chain2v *C, double v)
+{
+    size_t mark = A->top;
+    double *ai = (double *)ar_alloc(A, sizeof(double) * (size_t)(ma + 1));
+    OPS((a.d + 1) * (a.d + 2) + 5 * ma + 2);
+    for (int i = 0; i <= ma; ++i) {
+        double s = 0.0;
+        for (int j = a.d - i; j >= 0; --j) s = s * v + a.c[i * (a.d + 1) + j];
+        ai[i] = s;
+    }
+    int sign = 1;
+    if (ai[ma] == 0.0) { A->top = mark; return 1; }
+    double B = 0.0;
+    for (int k = 1; k <= ma; ++k) B = fmax(B, pow(fabs(ai[ma - k] / ai[ma]), 1.0 / k));
+    B = 2.0 * B;
+    if (!(B > 0.0)) B = 1.0;
+    double *w = (double *)ar_alloc(A, sizeof(double) * (size_t)(ma + 1));
+    double pw = 1.0;
+    for (int k = 0; k <= ma; ++k) { w[k] = ai[k] * pw; pw *= B; }
+    double roots[64];
+    int nr = isolate(A, w, ma, -1.0, 1.0, roots, 64);
+    for (int k = 0; k < nr; ++k) {
+        double al = roots[k] * B;
+        OPS(1);
+        if (k + 1 < nr && roots[k + 1] * B - al <= 1e-4 * fmax(1.0, fabs(al))) { ++k; continue; }
+        double kr;
+        double s = b2v_value(C, al, v, &kr);
+        if (kr < OR_KAPPA_SKIP) continue;
+        if (s < 0.0) sign = -sign;
+    }
+    A->top = mark;
+    return sign;
+}
+
 static void solve_2v(arena *A, const tri_t *T1, const tri_t *T2, v3 x0, v3 x3, const double *eta,
                      int ev1, int ev2, const or_sqrtfit *fit, const or_params *prm, int32_t qid,
                      or_sol *out, int32_t *nout, or_diag *dg)
@@ -1051,7 +1170,10 @@ static void solve_2v(arena *A, const tri_t *T1, const tri_t *T2, v3 x0, v3 x3, c
     /* piecewise sign scan of det R(v) on [0,1] */
     int P = prm->pieces;
     int *sg = (int *)ar_alloc(A, sizeof(int) * (size_t)(P + 1));
-#define DETSIGN(vv) (prm->det_method == 2 ? res_sign_paired(A, a, ma, b, (vv)) : \
+    chain2v C;
+    if (prm->det_method == 3) chain2v_setup(&C, T1, T2, x0, x3, eta, ev1, ev2, fit);
+#define DETSIGN(vv) (prm->det_method == 3 ? res_sign_chain(A, a, ma, &C, (vv)) : \
+                     prm->det_method == 2 ? res_sign_paired(A, a, ma, b, (vv)) : \
                      prm->det_method == 1 ? res_sign_product(A, a, ma, b, n, (vv)) : det_sign_at(A, a, b, n, (vv)))
     g_stage = 1;
     for (int j = 0; j <= P; ++j) sg[j] = DETSIGN((double)j / P);

@@ -128,7 +128,7 @@ def test_det_methods_agree_on_flat_slab(seed):
     N = np.array([[0, 0, -1.0]] * 3 + [[0, 0, 1.0]] * 3)
     tri = np.array([[0, 1, 2], [3, 4, 5]], dtype=np.int32)
     s0, d0 = oracle.solve_tt(P, N, tri, x0[None], x3[None], [0], [0], [0], [1], params=_params(0))
-    for m in (1, 2):
+    for m in (1, 2, 3):
         s1, d1 = oracle.solve_tt(P, N, tri, x0[None], x3[None], [0], [0], [0], [1], params=_params(m))
         assert len(s0) == len(s1) == 1
         for k in ("u1", "v1", "u2", "v2"):
@@ -148,11 +148,15 @@ def test_det_methods_on_sphere_neighbourhood():
     s0, d0 = oracle.solve_tt(*args, params=_params(0))
     s1, d1 = oracle.solve_tt(*args, params=_params(1))
     s2, d2 = oracle.solve_tt(*args, params=_params(2))
+    s3, d3 = oracle.solve_tt(*args, params=_params(3))
     print(f"{n} tuples: sign changes GE {d0['n_vroots'].sum()} product {d1['n_vroots'].sum()} "
-          f"paired {d2['n_vroots'].sum()}; valid GE {len(s0)} product {len(s1)} paired {len(s2)}")
+          f"paired {d2['n_vroots'].sum()} chain {d3['n_vroots'].sum()}; valid GE {len(s0)} product {len(s1)} "
+          f"paired {len(s2)} chain {len(s3)}")
     assert len(s1) >= 1
     k0 = {(int(s['query']), round(s['u1'], 8), round(s['v1'], 8)) for s in s0}
     k1 = {(int(s['query']), round(s['u1'], 8), round(s['v1'], 8)) for s in s1}
     k2 = {(int(s['query']), round(s['u1'], 8), round(s['v1'], 8)) for s in s2}
-    assert k0 == k1 == k2
+    k3 = {(int(s['query']), round(s['u1'], 8), round(s['v1'], 8)) for s in s3}
+    assert k0 == k1 == k2 == k3
+    assert d3["n_vroots"].sum() <= d2["n_vroots"].sum()
     assert d0["n_vroots"].sum() > d1["n_vroots"].sum()
