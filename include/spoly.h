@@ -255,7 +255,8 @@ spoly_status spoly_cull_2bounce(spoly_ctx *ctx, const spoly_mesh *mesh,
  * of the 6 pieces; NULL selects the library's minimax table.  The sign of
  * det R(v) is sampled at v = j/pieces (1 <= pieces <= 4095) and each sign
  * change is refined by bisect_iters (<= 40) bisection steps; near-double root
- * pairs of a(., v) are left out of the sign's product.  Every candidate is polished
+ * pairs of a(., v), and roots where the mapped ray from x1 runs within 1e-4 rad
+ * of T2's plane (x2 at infinity), are left out of the sign's product.  Every candidate is polished
  * in FP64 on the exact constraints (the approximation only brackets roots).
  * prec must be SPOLY_FP64.  Records carry tri[0..1] and (u,v) of both vertices.
  * counters / diag_q as for spoly_solve_1bounce ([0] counts sign changes).

@@ -38,6 +38,7 @@ struct TTGeo {
     int f1, f2;                                 // 1 = interpolated normals, 0 = flat
     int ev1, ev2;                               // SPOLY_R or SPOLY_T at x1, x2
     V3<double> edge2;                           // product-form edge of T2 (reflection at x2)
+    double n2len;                               // |e21 x e22|
 };
 
 __device__ __forceinline__ V3<double> ld3t(const double* x, const double* y, const double* z, int i)
@@ -116,6 +117,7 @@ __device__ void tt_setup(const TTArgs& A, int64_t q, TTGeo& g)
     g.ev1 = A.ev1;
     g.ev2 = A.ev2;
     g.edge2 = tt_edge(c2, c1, g.x3, g.e21, g.e22);
+    g.n2len = len(cross(g.e21, g.e22));
 }
 
 // ------------------------------------------------------------------ LDS bivariate polynomials (wave-cooperative)
@@ -471,7 +473,9 @@ __device__ __forceinline__ unsigned iso_level(const double (&c)[DMAX + 1], doubl
 }
 
 // ------------------------------------------------------------------ b(u,v) through its defining products
-__device__ __forceinline__ double tt_b_eval(const TTGeo& g, double u, double v)
+// b(u, v) from its defining products; with kr, also |kappa| / (|Dt| |e21 x e22|),
+// the sine of the angle between the mapped ray from x1 and T2's plane
+__device__ __forceinline__ double tt_b_eval(const TTGeo& g, double u, double v, double* kr = nullptr)
 {
     V3<double> x1 = g.p1 + g.e11 * u + g.e12 * v;
     V3<double> n1 = g.n10 + (g.dn11 * u + g.dn12 * v) * double(g.f1);
@@ -492,6 +496,10 @@ __device__ __forceinline__ double tt_b_eval(const TTGeo& g, double u, double v)
     V3<double> X2 = g.p2 * ka + g.e21 * ut + g.e22 * vt;
     V3<double> M2 = g.n20 * ka + (g.dn21 * ut + g.dn22 * vt) * double(g.f2);
     V3<double> D2 = g.x3 * ka - X2;
+    if (kr) {
+        const double ld = len(Dt) * g.n2len;
+        *kr = ld > 0.0 ? fabs(ka) / ld : 0.0;
+    }
     if (g.ev2 == SPOLY_R) {
         const V3<double> t = cross(M2, g.edge2);
         return dot(Dt, M2) * dot(D2, t) + dot(Dt, t) * dot(D2, M2);
@@ -536,8 +544,25 @@ __device__ __forceinline__ double root_k_upper(double x, int k)
 // rounding noise.
 constexpr double kPairGap = 1e-4;
 
+// Roots of a(., v) where the mapped ray from x1 runs within this angle (rad)
+// of T2's plane put x2 at infinity: no path lies there, and where T2 is flat
+// or its normals are proportional to its positions (a sphere) kappa divides
+// both a and b, so the resultant vanishes identically and the sign of b at
+// such a root is rounding.  They are left out of the product.
+constexpr double kKappaSkip = 1e-4;
+
+// sgn b at a root of a(., v) taken into the product: -1, or +1 (also for a
+// root left out at x2 = infinity)
+__device__ __forceinline__ bool factor_negative(const TTGeo& g, double u, double v)
+{
+    double kr;
+    const double b = tt_b_eval(g, u, v, &kr);
+    return kr >= kKappaSkip && b < 0.0;
+}
+
 // Product of sgn b(x B, v) over the real roots x in [-1, 1] of the scaled
-// a(., v) (coefficients c, degree at most D), near-double pairs left out.
+// a(., v) (coefficients c, degree at most D), near-double pairs and roots at
+// x2 = infinity left out.
 template <int D>
 __device__ __forceinline__ int sign_over_roots(const TTGeo& g, const double (&c)[kDA + 1], double B, double v)
 {
@@ -563,11 +588,11 @@ __device__ __forceinline__ int sign_over_roots(const TTGeo& g, const double (&c)
             has_p = false;
             continue;
         }
-        if (has_p && tt_b_eval(g, p, v) < 0.0) s = -s;
+        if (has_p && factor_negative(g, p, v)) s = -s;
         p = x;
         has_p = true;
     }
-    if (has_p && tt_b_eval(g, p, v) < 0.0) s = -s;
+    if (has_p && factor_negative(g, p, v)) s = -s;
     return s;
 }
 
