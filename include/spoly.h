@@ -101,6 +101,13 @@ typedef struct {
                                            /* the precision argument says                  */
 #define SPOLY_FLAG_STAGE_TIMES  (1u << 2)  /* one-vertex solve: record timing events       */
                                            /* around its kernels (spoly_stage_times)       */
+#define SPOLY_FLAG_DETERMINISTIC_ORDER (1u << 3)  /* sort the records written by (query,   */
+                                           /* v[0], u[0]) on the device after the solve,   */
+                                           /* so one input gives one output order (the     */
+                                           /* solves reserve output slots with atomics);   */
+                                           /* the context grows an ~80 B-per-record        */
+                                           /* workspace; not for the no-allocation entry   */
+                                           /* point (E_UNSUPPORTED) nor the mixed solve    */
 
 /* One admissible chain.  For one vertex tri[1] = -1 and u[1] = v[1] = 0. */
 typedef struct {

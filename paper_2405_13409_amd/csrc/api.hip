@@ -14,6 +14,7 @@
 #include "pruner.hpp"
 #include "mixed.hpp"
 #include "tail.hpp"
+#include "order.hpp"
 
 struct spoly_ctx {
     int device;
@@ -31,6 +32,8 @@ struct spoly_ctx {
     int64_t ob_rbytes;
     hipEvent_t stage_ev[5];  // timing events of the last one-vertex solve with SPOLY_FLAG_STAGE_TIMES
     int stage_n;             // kernels timed by stage_ev (0: none yet)
+    void* ord_block;         // workspace of SPOLY_FLAG_DETERMINISTIC_ORDER, grown on demand
+    size_t ord_bytes;
 };
 
 namespace {
@@ -42,6 +45,22 @@ bool mesh_ok(const spoly_mesh* m)
 bool pts_ok(const spoly_points* p) { return p && p->x && p->y && p->z && p->n > 0; }
 
 spoly_status dev_err(hipError_t e) { return e == hipSuccess ? SPOLY_OK : SPOLY_E_DEVICE; }
+
+// SPOLY_FLAG_DETERMINISTIC_ORDER: sort the records the solve just wrote (same stream)
+spoly_status sort_output(spoly_ctx* ctx, spoly_solution* out, int64_t cap, const unsigned long long* count,
+                         hipStream_t s)
+{
+    if (cap <= 0) return SPOLY_OK;
+    const size_t need = spoly::sort_solutions_bytes(cap);
+    if (ctx->ord_bytes < need) {
+        if (ctx->ord_block) (void)hipFree(ctx->ord_block);
+        ctx->ord_block = nullptr;
+        ctx->ord_bytes = 0;
+        if (hipMalloc(&ctx->ord_block, need) != hipSuccess) return SPOLY_E_DEVICE;
+        ctx->ord_bytes = need;
+    }
+    return dev_err(spoly::sort_solutions(out, cap, count, ctx->ord_block, ctx->ord_bytes, s));
+}
 
 }  // namespace
 
@@ -111,6 +130,7 @@ void spoly_ctx_destroy(spoly_ctx* ctx)
     if (ctx->pw_block) (void)hipFree(ctx->pw_block);
     if (ctx->ob_block) (void)hipFree(ctx->ob_block);
     if (ctx->ob_rblock) (void)hipFree(ctx->ob_rblock);
+    if (ctx->ord_block) (void)hipFree(ctx->ord_block);
     if (ctx->stage_ev[0])
         for (int i = 0; i < 5; ++i) (void)hipEventDestroy(ctx->stage_ev[i]);
     std::free(ctx);
@@ -257,8 +277,10 @@ spoly_status spoly_solve_1bounce(spoly_ctx* ctx, const spoly_mesh* mesh, const s
         evs = ctx->stage_ev;
         ctx->stage_n = n_queries > 0 ? (ev == SPOLY_T ? 4 : 3) : 0;
     }
-    return dev_err(spoly::launch_onebounce_2phase(A, int(ev), int(prec), ctx->cus * 4,
-                                                  static_cast<hipStream_t>(stream), evs));
+    st = dev_err(spoly::launch_onebounce_2phase(A, int(ev), int(prec), ctx->cus * 4,
+                                                static_cast<hipStream_t>(stream), evs));
+    if (st != SPOLY_OK || !(params->flags & SPOLY_FLAG_DETERMINISTIC_ORDER)) return st;
+    return sort_output(ctx, out, out_capacity, out_count, static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"
@@ -281,7 +303,8 @@ static spoly_status ob_args(const spoly_mesh* mesh, const spoly_points* x0s, con
     if (!(params->tau > 0.0) || !(params->iso_eps > 0.0) || params->polish_iters < 0 || !(params->u_margin >= 0.0) ||
         !(params->dedup >= 0.0))
         return SPOLY_E_INVALID_ARG;
-    if (params->flags & ~(SPOLY_FLAG_FORCE_FP64 | SPOLY_FLAG_STAGE_TIMES)) return SPOLY_E_INVALID_ARG;
+    if (params->flags & ~(SPOLY_FLAG_FORCE_FP64 | SPOLY_FLAG_STAGE_TIMES | SPOLY_FLAG_DETERMINISTIC_ORDER))
+        return SPOLY_E_INVALID_ARG;
     if (params->flags & SPOLY_FLAG_FORCE_FP64) prec = SPOLY_FP64;
     A.px = mesh->px; A.py = mesh->py; A.pz = mesh->pz;
     A.nx = mesh->nx; A.ny = mesh->ny; A.nz = mesh->nz;
@@ -354,6 +377,8 @@ spoly_status spoly_solve_1bounce_noalloc(const spoly_mesh* mesh, const spoly_poi
     spoly_status st = ob_args(mesh, x0s, x2s, q_x0, q_x2, q_tri, n_queries, ev, eta0, eta1, prec, params, out,
                               out_capacity, out_count, counters, diag_q, A);
     if (st != SPOLY_OK) return st;
+    // the sort needs a workspace sized by the output capacity
+    if (params->flags & SPOLY_FLAG_DETERMINISTIC_ORDER) return SPOLY_E_UNSUPPORTED;
     if (params->flags & SPOLY_FLAG_FORCE_FP64) prec = SPOLY_FP64;
     const int64_t max_q = ev == SPOLY_T ? SPOLY_NOALLOC_MAX_QUERIES_T : SPOLY_NOALLOC_MAX_QUERIES_R;
     if (n_queries > max_q) return SPOLY_E_CAPACITY;
@@ -445,6 +470,7 @@ spoly_status spoly_solve_nbounce(spoly_ctx* ctx, const spoly_mesh* mesh, int32_t
     // a reflection keeps its medium: equal IORs on its two segments
     for (int i = 0; i < 2; ++i)
         if (chain[i] == SPOLY_R && eta[i] != eta[i + 1]) return SPOLY_E_INVALID_ARG;
+    if (params->flags & ~(SPOLY_FLAG_FORCE_FP64 | SPOLY_FLAG_DETERMINISTIC_ORDER)) return SPOLY_E_INVALID_ARG;
     if (params->pieces < 1 || params->pieces > spoly::kMaxPieces || params->bisect_iters < 0 ||
         params->bisect_iters > spoly::kMaxBisect ||
         params->polish_iters < 0 ||
@@ -468,7 +494,9 @@ spoly_status spoly_solve_nbounce(spoly_ctx* ctx, const spoly_mesh* mesh, int32_t
     A.tau = params->tau; A.u_margin = params->u_margin; A.dedup = params->dedup;
     A.out = out; A.cap = out_capacity; A.out_count = out_count;
     A.counters = counters; A.diag_q = diag_q;
-    return dev_err(spoly::launch_tt_solve(A, static_cast<hipStream_t>(stream)));
+    spoly_status st = dev_err(spoly::launch_tt_solve(A, static_cast<hipStream_t>(stream)));
+    if (st != SPOLY_OK || !(params->flags & SPOLY_FLAG_DETERMINISTIC_ORDER)) return st;
+    return sort_output(ctx, out, out_capacity, out_count, static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"
@@ -600,6 +628,9 @@ extern "C" spoly_status spoly_solve_mixed(spoly_ctx* ctx, const spoly_mesh* mesh
     if (shape->workgroups_per_cu < 1 || shape->workgroups_per_cu > 32 || shape->r_tile < 64 ||
         shape->r_tile > 4096 || (shape->r_tile % 64) != 0 || shape->order < 0 || shape->order > 2)
         return SPOLY_E_INVALID_ARG;
+    if (params->flags & SPOLY_FLAG_DETERMINISTIC_ORDER) return SPOLY_E_UNSUPPORTED;
+    if (params->flags & ~SPOLY_FLAG_FORCE_FP64) return SPOLY_E_INVALID_ARG;
+    if (params->flags & SPOLY_FLAG_FORCE_FP64) prec = SPOLY_FP64;
     if (params->pieces < 1 || params->pieces > spoly::kMaxPieces || params->bisect_iters < 0 ||
         params->bisect_iters > spoly::kMaxBisect ||
         params->polish_iters < 0 || !(params->tau > 0.0) || !(params->iso_eps > 0.0) || !(params->u_margin >= 0.0) ||

@@ -8,3 +8,4 @@
 #include "pruner.hip"
 #include "mixed.hip"
 #include "tail.hip"
+#include "order.hip"

@@ -31,6 +31,7 @@ EXPORTED = ("spoly_ctx_create", "spoly_ctx_destroy", "spoly_default_params", "sp
             "spoly_bvh_build", "spoly_bvh_destroy", "spoly_tail_default_params", "spoly_path_tail")
 SPOLY_FLAG_FORCE_FP64 = 1 << 1
 SPOLY_FLAG_STAGE_TIMES = 1 << 2
+SPOLY_FLAG_DETERMINISTIC_ORDER = 1 << 3
 PRUNER_NPARAMS = 38657
 
 
