@@ -215,7 +215,11 @@ __global__ void k_adam(float* p, const float* g, float* m, float* v, int64_t n, 
 // activations go through a 16 x 128 bf16 LDS buffer between layers (the D
 // fragment layout of one layer is not the A fragment layout of the next).
 constexpr int kW1 = kHid * kFeat, kW2 = kHid * kHid, kW4 = 16 * kHid;
-constexpr int kPruneLds = (kW1 + 2 * kW2 + kW4) * 2 + 4 * 16 * kHid * 2;
+// 8 waves per block share one copy of the weights (80 KB) and own a 4 KB
+// activation buffer each: 112 KB of the CU's 160 KB, two waves per SIMD
+// (the register budget of the kernel allows no more).
+constexpr int kPruneWaves = 8;
+constexpr int kPruneLds = (kW1 + 2 * kW2 + kW4) * 2 + kPruneWaves * 16 * kHid * 2;
 
 __device__ __forceinline__ v4s lds4(const unsigned short* p)
 {
@@ -245,7 +249,7 @@ __device__ __forceinline__ void layer16(const unsigned short* act /*[16][KIN] bf
     }
 }
 
-__global__ void __launch_bounds__(256) k_prune_score(PrunerIO io, const float* params, float threshold,
+__global__ void __launch_bounds__(kPruneWaves * 64) k_prune_score(PrunerIO io, const float* params, float threshold,
                                                      float* scores, int32_t* keep_idx, int64_t cap,
                                                      unsigned long long* keep_count)
 {
@@ -254,7 +258,7 @@ __global__ void __launch_bounds__(256) k_prune_score(PrunerIO io, const float* p
     unsigned short* W2t = W1t + kW1;       // [128][128]
     unsigned short* W3t = W2t + kW2;
     unsigned short* W4t = W3t + kW2;       // [16][128], row 0 real
-    unsigned short* act = W4t + kW4;       // 4 waves x [16][128]
+    unsigned short* act = W4t + kW4;       // kPruneWaves x [16][128]
     const PrunerLayout L;
     for (int i = threadIdx.x; i < kW1; i += blockDim.x) {
         const int o = i / kFeat, k = i % kFeat;
@@ -274,7 +278,8 @@ __global__ void __launch_bounds__(256) k_prune_score(PrunerIO io, const float* p
     const int r = lane & 15, kq = (lane >> 4) * 4;
     unsigned short* my = act + w * 16 * kHid;
     const int64_t ntile = (io.n + 15) / 16;
-    for (int64_t tile = int64_t(blockIdx.x) * 4 + w; tile < ntile; tile += int64_t(gridDim.x) * 4) {
+    for (int64_t tile = int64_t(blockIdx.x) * kPruneWaves + w; tile < ntile;
+         tile += int64_t(gridDim.x) * kPruneWaves) {
         const int64_t q0 = tile * 16;
         // gather features of 16 tuples: lane handles tuple r, features kq.. in chunks
         {
@@ -395,11 +400,17 @@ hipError_t launch_prune_score(const PrunerIO& io, const float* params, float thr
         (void)hipFuncSetAttribute((const void*)k_prune_score, hipFuncAttributeMaxDynamicSharedMemorySize, kPruneLds);
         attr = true;
     }
+    // persistent: one block per compute unit (its LDS allows no second), each
+    // loading the weights once and striding over 16-tuple tiles
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;
     const int64_t tiles = (io.n + 15) / 16;
-    int64_t blocks = (tiles + 3) / 4;
-    if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_prune_score, dim3(unsigned(blocks)), dim3(256), kPruneLds, s, io, params, threshold, scores,
-                       keep_idx, cap, keep_count);
+    int64_t blocks = (tiles + kPruneWaves - 1) / kPruneWaves;
+    if (blocks > cus) blocks = cus;
+    hipLaunchKernelGGL(k_prune_score, dim3(unsigned(blocks)), dim3(kPruneWaves * 64), kPruneLds, s, io, params,
+                       threshold, scores, keep_idx, cap, keep_count);
     return hipGetLastError();
 }
 
