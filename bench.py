@@ -39,8 +39,8 @@ VALU_ISSUE = 256 * 4 * 2.4e9 / 4
 OPS = {
     "glints_R": (783, 1264, 440, 71),
     "glints_T": (1439, 7075, 894, 102),
-    "caustic_TT": (368162, 1154952, 1316046, 7323),
-    "mirror_RR": (17860, 874785, 38675, 650),
+    "caustic_TT": (368162, 936311, 9924, 127),
+    "mirror_RR": (17860, 899708, 44109, 704),
 }
 PRUNER_FLOP = 2 * (42 * 128 + 2 * 128 * 128 + 128)   # multiply-adds of the four dense layers, per tuple
 

@@ -157,3 +157,32 @@ def test_tt_cull_bounds_against_oracle_twin(sp, ctx):
     loose = oracle.cull_tt(mesh.P, mesh.N, mesh.tri, R, x3, (1.0, 1.5, 1.0), 3e-3)
     assert np.all(gk[tight]), "GPU cull dropped a tuple the FP64 twin keeps"
     assert np.all(loose[gk]), "GPU cull kept a tuple outside the widened FP64 twin"
+
+
+def test_tt_exhaustive_receivers_parity(sp, ctx):
+    """Every GPU-culled tuple of every 512th receiver of the 64x64 caustic
+    grid, in the order the benchmark solves them: the whole solution sets
+    against the oracle's, and the sign-change count of each tuple's scan."""
+    from paper_2405_13409_amd import caustic
+
+    _tag("tt exhaustive receivers")
+    mesh = scenes.caustic_sphere()
+    x3 = scenes.CAUSTIC_LIGHT_OUTSIDE
+    rec = scenes.caustic_receivers()[::512]
+    dm = sp.DeviceMesh(mesh.P, mesh.N, mesh.tri)
+    d0, dl = sp.DevicePoints(rec), sp.DevicePoints(x3)
+    T = caustic.cull_sorted(ctx, dm, d0, dl)
+    dq = torch.zeros(2 * T.n, dtype=torch.int32, device="cuda")
+    g = ctx.solve_2bounce(dm, d0, dl, T.q0, T.q3, T.qt, diag=dq)
+    torch.cuda.synchronize()
+    q0, q3, qt = T.q0.cpu().numpy(), T.q3.cpu().numpy(), T.qt.cpu().numpy().reshape(-1, 2)
+    threads = oracle.set_threads(16)
+    try:
+        o, od = oracle.solve_tt(mesh.P, mesh.N, mesh.tri, rec, x3, q0, q3, qt[:, 0], qt[:, 1])
+    finally:
+        oracle.set_threads(threads)
+    n, nb = _compare_tt(g, o, T.n)
+    same = float(np.mean(dq.cpu().numpy().reshape(-1, 2)[:, 0] == od["n_vroots"]))
+    print(f"{T.n} tuples of {len(rec)} receivers: {len(o)} oracle paths, compared {n}, excluded {nb}; "
+          f"sign-change counts equal on {same:.5f} of the tuples")
+    assert T.n > 100000 and nb <= 0.001 * T.n and same >= 0.999
