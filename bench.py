@@ -46,26 +46,27 @@ PRUNER_FLOP = 2 * (42 * 128 + 2 * 128 * 128 + 128)   # multiply-adds of the four
 
 # HBM bytes of the reflection front kernel k_ob_front<float,R> on the glints workload, from rocprofv3 --pmc
 # FETCH_SIZE and WRITE_SIZE (KiB per dispatch), scaled by what the same counters read for a plain 256 MiB
-# device copy.  Valid only for the kernel sources they were taken on (sha256 prefix over _KERNEL_SOURCES,
-# the cull included: it sets the order of the candidates); otherwise traffic is null.
-TRAFFIC_FRONT = {"sha": "0a935f5b0a43f05d", "candidates": 99118956, "fetch_kib": 680467.2, "write_kib": 1900542.1,
+# device copy.  Valid only for the one-vertex kernel sources they were taken on (sha256 prefix over
+# ONE_VERTEX_SOURCES, the cull included: it sets the order of the candidates); otherwise traffic is null.
+ONE_VERTEX_SOURCES = ("onebounce.hip", "spoly_dev.hpp", "laplace_gen.inc", "onebounce.hpp", "cull.hip")
+TWO_VERTEX_SOURCES = ("twobounce.hip", "twobounce.hpp", "spoly_dev.hpp")
+TRAFFIC_FRONT = {"sha": "5a6437caecab97fa", "candidates": 99118956, "fetch_kib": 680467.2, "write_kib": 1900542.1,
                  "fetch_scale": 262144.0 / 131083.5, "write_scale": 262144.0 / 262144.0}
 # VALU wave-instructions (rocprofv3 --pmc SQ_INSTS_VALU) per launch of each one-vertex kernel on the glints
-# workload, and per tuple of the two-vertex solve on the RR and TT legs, under the same source check
-# (profiles/valu_counters.md).
-VALU_INSTS = {"sha": "0a935f5b0a43f05d",
+# workload, and per tuple of the two-vertex solve on the RR and TT legs, each group under the source check of
+# its own kernels (profiles/valu_counters.md).
+VALU_INSTS = {"sha": "5a6437caecab97fa",
               "k_ob_front_R": 2.917e9, "k_ob_back_R": 5.977e8, "k_ob_full_R": 4.107e7,
-              "k_ob_coef_T": 6.219e8, "k_ob_iso_T": 1.690e8, "k_ob_back_T": 1.497e8,
-              "k_tt_solve_RR_per_tuple": 1.438e12 / 9256723, "k_tt_solve_TT_per_tuple": 1.976e12 / 6477601}
-_KERNEL_SOURCES = ("onebounce.hip", "spoly_dev.hpp", "laplace_gen.inc", "onebounce.hpp", "cull.hip",
-                   "twobounce.hip", "twobounce.hpp", "pruner.hip")
+              "k_ob_coef_T": 6.219e8, "k_ob_iso_T": 1.690e8, "k_ob_back_T": 1.497e8}
+VALU_INSTS_TT = {"sha": "cf26ff7045800656",
+                 "k_tt_solve_RR_per_tuple": 1.438e12 / 9256723, "k_tt_solve_TT_per_tuple": 1.976e12 / 6477601}
 
 
-def _kernel_sha() -> str:
+def _kernel_sha(files=ONE_VERTEX_SOURCES) -> str:
     import hashlib
 
     h = hashlib.sha256()
-    for f in _KERNEL_SOURCES:
+    for f in files:
         with open(os.path.join(ROOT, "paper_2405_13409_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -75,7 +76,7 @@ def traffic_bytes(candidates: int):
     """HBM bytes per front launch for `candidates` instances, or None if the
     kernels changed since the counters were taken."""
     t = TRAFFIC_FRONT
-    if t is None or _kernel_sha() != t["sha"]:
+    if _kernel_sha() != t["sha"]:
         return None
     per = (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024.0 / t["candidates"]
     return per * candidates
@@ -84,14 +85,15 @@ def traffic_bytes(candidates: int):
 def valu_insts(kernel: str, instances: int | None = None):
     """VALU wave-instructions of one launch (per-instance figures scaled by
     `instances`), or None if the kernels changed since they were counted."""
-    t = VALU_INSTS
-    if t is None or _kernel_sha() != t["sha"]:
-        return None
-    if kernel in t:
-        return t[kernel]
-    if instances is not None and kernel + "_per_tuple" in t:
+    if kernel.startswith("k_tt_solve"):
+        t = VALU_INSTS_TT
+        if _kernel_sha(TWO_VERTEX_SOURCES) != t["sha"] or instances is None or kernel + "_per_tuple" not in t:
+            return None
         return t[kernel + "_per_tuple"] * instances
-    return None
+    t = VALU_INSTS
+    if _kernel_sha() != t["sha"]:
+        return None
+    return t.get(kernel)
 
 
 def kernel_obj(name, flop, ms, peak, dtype, insts=None, **extra):

@@ -393,9 +393,15 @@ __device__ __forceinline__ void horner_lv(const double (&c)[DMAX + 1], double x,
     }
 }
 
+// Roots of the derivative levels (d < DMAX) only split the next level into
+// monotone pieces: they stop at 1e-9 relative, three orders below the
+// near-double pair gap of the det-sign product (closer roots are left out of
+// it), so a coarser piece end cannot change which roots a sign change brackets;
+// the roots of the polynomial itself are refined to full precision.
 template <int DMAX, int d>
 __device__ __forceinline__ double refine(const double (&c)[DMAX + 1], double l, double r, bool neg_l)
 {
+    constexpr double tol = d == DMAX ? 4e-16 : 1e-9;
     double x = 0.5 * (l + r);
     for (int it = 0; it < 100; ++it) {
         double f, fp;
@@ -406,7 +412,7 @@ __device__ __forceinline__ double refine(const double (&c)[DMAX + 1], double l, 
         double xn = x - f / fp;
         if (!(xn > l && xn < r)) xn = 0.5 * (l + r);
         if (!(r - l > 0.0) || xn == x) return xn;
-        if (fabs(xn - x) <= 4e-16 * fmax(1.0, fabs(x))) return xn;
+        if (fabs(xn - x) <= tol * fmax(1.0, fabs(x))) return xn;
         x = xn;
     }
     return x;
