@@ -58,8 +58,8 @@ TRAFFIC_FRONT = {"sha": "5a6437caecab97fa", "candidates": 99118956, "fetch_kib":
 VALU_INSTS = {"sha": "5a6437caecab97fa",
               "k_ob_front_R": 2.917e9, "k_ob_back_R": 5.977e8, "k_ob_full_R": 4.107e7,
               "k_ob_coef_T": 6.219e8, "k_ob_iso_T": 1.690e8, "k_ob_back_T": 1.497e8}
-VALU_INSTS_TT = {"sha": "cf26ff7045800656",
-                 "k_tt_solve_RR_per_tuple": 1.438e12 / 9256723, "k_tt_solve_TT_per_tuple": 1.976e12 / 6477601}
+VALU_INSTS_TT = {"sha": "f58d82b1cfe5371b",
+                 "k_tt_solve_RR_per_tuple": 7.352e11 / 9256723, "k_tt_solve_TT_per_tuple": 4.501e11 / 6477601}
 
 
 def _kernel_sha(files=ONE_VERTEX_SOURCES) -> str:
