@@ -97,3 +97,30 @@ def test_noalloc_rejects_oversize_and_bad_args_on_host():
                                            lim + 1, ev, 1.0, 1.0, 0, ctypes.byref(p), None, 0, ctypes.byref(cnt),
                                            None, None, None)
         assert st == spoly.SPOLY_E_CAPACITY
+
+
+def test_tail_entry_points_on_host():
+    """The path-phase tail's defaults and its argument checks before any
+    device call; a null hierarchy handle is ignored by the destroy call."""
+    from paper_2405_13409_amd import spoly
+
+    L = _lib()
+    p = spoly.tail_default_params()
+    assert (p.intensity, p.reflectance, p.t_eps, tuple(p.rcv_normal)) == (1.0, 1.0, 1e-6, (0.0, 0.0, 0.0))
+    L.spoly_bvh_destroy(None)
+    h = ctypes.c_void_p()
+    assert L.spoly_bvh_build(None, None, ctypes.byref(h), None) == spoly.SPOLY_E_INVALID_ARG
+    chain = (ctypes.c_int * 1)(spoly.SPOLY_R)
+    eta = (ctypes.c_double * 2)(1.0, 1.0)
+    st = L.spoly_path_tail(None, None, None, 1, chain, eta, None, None, None, None, None, 0, None, ctypes.byref(p),
+                           None, None, None, None)
+    assert st == spoly.SPOLY_E_INVALID_ARG
+
+
+def test_flag_bits():
+    from paper_2405_13409_amd import spoly
+
+    bits = (spoly.SPOLY_FLAG_FORCE_FP64, spoly.SPOLY_FLAG_STAGE_TIMES, spoly.SPOLY_FLAG_DETERMINISTIC_ORDER)
+    assert len(set(bits)) == 3 and all(b & (b - 1) == 0 for b in bits)
+    txt = open(os.path.join(ROOT, "include", "spoly.h")).read()
+    assert "SPOLY_FLAG_DETERMINISTIC_ORDER (1u << 3)" in txt
