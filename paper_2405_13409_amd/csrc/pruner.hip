@@ -210,55 +210,75 @@ __global__ void k_adam(float* p, const float* g, float* m, float* v, int64_t n, 
 }
 
 // ------------------------------------------------------------------ fused inference
-// Weights in LDS, transposed to [out][in] so that each lane's four consecutive
-// k of a B fragment are one 8-byte read.  A wave scores 16 tuples per tile:
-// activations go through a 16 x 128 bf16 LDS buffer between layers (the D
-// fragment layout of one layer is not the A fragment layout of the next).
+// One 16-tuple tile per wave, activations kept in registers: every layer
+// computes H^T = W^T X^T on the matrix cores (weights as the A operand, the
+// tile's activations as B).  Its D fragment -- lane l holds tuple l & 15 and
+// four consecutive output neurons 4 (l >> 4) .. + 3 of each 16-neuron tile --
+// is then exactly the B fragment of the next layer's 16-neuron k-block, so no
+// activation goes through LDS.  Weights and biases sit in LDS, transposed to
+// [out][in] so that a lane's four consecutive k of an A fragment are one
+// 8-byte read; the output layer's row 0 leaves each tuple's logit in lanes
+// 0..15.
 constexpr int kW1 = kHid * kFeat, kW2 = kHid * kHid, kW4 = 16 * kHid;
-// 8 waves per block share one copy of the weights (80 KB) and own a 4 KB
-// activation buffer each: 112 KB of the CU's 160 KB, two waves per SIMD
-// (the register budget of the kernel allows no more).
-constexpr int kPruneWaves = 8;
-constexpr int kPruneLds = (kW1 + 2 * kW2 + kW4) * 2 + kPruneWaves * 16 * kHid * 2;
+constexpr int kPruneWaves = 12;
+constexpr int kPruneLds = (kW1 + 2 * kW2 + kW4) * 2 + 4 * kHid * 4;
 
-__device__ __forceinline__ v4s lds4(const unsigned short* p)
+typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+
+// four floats as a bf16 fragment (round to nearest even, native conversion)
+__device__ __forceinline__ v4s frag4(float a, float b, float c, float d)
 {
-    const uint2 u = *reinterpret_cast<const uint2*>(p);
-    v4s r;
-    r[0] = (short)(u.x & 0xffffu); r[1] = (short)(u.x >> 16);
-    r[2] = (short)(u.y & 0xffffu); r[3] = (short)(u.y >> 16);
-    return r;
+    const bf2v lo = __builtin_convertvector((f2v){a, b}, bf2v);
+    const bf2v hi = __builtin_convertvector((f2v){c, d}, bf2v);
+    uint2 u;
+    u.x = __builtin_bit_cast(unsigned int, lo);
+    u.y = __builtin_bit_cast(unsigned int, hi);
+    return __builtin_bit_cast(v4s, u);
 }
 
-template <int KIN>
-__device__ __forceinline__ void layer16(const unsigned short* act /*[16][KIN] bf16*/, const unsigned short* wt /*[out][KIN]*/,
-                                        int nout_tiles, v4f (&acc)[8])
+template <int KB, int NT>
+__device__ __forceinline__ void layer_t(const unsigned short* wt /*[NT*16][KB*16]*/, const v4s (&x)[KB],
+                                        v4f (&acc)[NT])
 {
     const int lane = lane_id(), r = lane & 15, kq = (lane >> 4) * 4;
 #pragma unroll
-    for (int nt = 0; nt < 8; ++nt) acc[nt] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int nt = 0; nt < NT; ++nt) acc[nt] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int k0 = 0; k0 < KIN; k0 += 16) {
-        const v4s a = lds4(act + r * KIN + k0 + kq);
+    for (int kb = 0; kb < KB; ++kb) {
 #pragma unroll
-        for (int nt = 0; nt < 8; ++nt)
-            if (nt < nout_tiles) {
-                const v4s b = lds4(wt + (nt * 16 + r) * KIN + k0 + kq);
-                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[nt], 0, 0, 0);
-            }
+        for (int nt = 0; nt < NT; ++nt) {
+            const v4s w = *reinterpret_cast<const v4s*>(wt + (nt * 16 + r) * (KB * 16) + kb * 16 + kq);
+            acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w, x[kb], acc[nt], 0, 0, 0);
+        }
+        // keep the weight reads of one k-block in flight at a time (the
+        // scheduler would otherwise hoist a whole layer's and spill)
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// bias + ReLU of the eight output tiles, as the next layer's B fragments
+__device__ __forceinline__ void relu_frags(const v4f (&acc)[8], const float* bias, v4s (&x)[8])
+{
+    const int kq = (lane_id() >> 4) * 4;
+#pragma unroll
+    for (int nt = 0; nt < 8; ++nt) {
+        const float* bb = bias + nt * 16 + kq;
+        x[nt] = frag4(fmaxf(acc[nt][0] + bb[0], 0.f), fmaxf(acc[nt][1] + bb[1], 0.f),
+                      fmaxf(acc[nt][2] + bb[2], 0.f), fmaxf(acc[nt][3] + bb[3], 0.f));
     }
 }
 
 __global__ void __launch_bounds__(kPruneWaves * 64) k_prune_score(PrunerIO io, const float* params, float threshold,
-                                                     float* scores, int32_t* keep_idx, int64_t cap,
-                                                     unsigned long long* keep_count)
+                                                                float* scores, int32_t* keep_idx, int64_t cap,
+                                                                unsigned long long* keep_count)
 {
     extern __shared__ unsigned short sm[];
     unsigned short* W1t = sm;              // [128][48]
     unsigned short* W2t = W1t + kW1;       // [128][128]
     unsigned short* W3t = W2t + kW2;
     unsigned short* W4t = W3t + kW2;       // [16][128], row 0 real
-    unsigned short* act = W4t + kW4;       // kPruneWaves x [16][128]
+    float* bias = reinterpret_cast<float*>(W4t + kW4);   // b1, b2, b3 [128 each], b4
     const PrunerLayout L;
     for (int i = threadIdx.x; i < kW1; i += blockDim.x) {
         const int o = i / kFeat, k = i % kFeat;
@@ -273,96 +293,59 @@ __global__ void __launch_bounds__(kPruneWaves * 64) k_prune_score(PrunerIO io, c
         const int o = i / kHid, k = i % kHid;
         W4t[i] = o == 0 ? f2bf(params[L.w4 + k]) : (unsigned short)0;
     }
+    for (int i = threadIdx.x; i < kHid; i += blockDim.x) {
+        bias[i] = params[L.b1 + i];
+        bias[kHid + i] = params[L.b2 + i];
+        bias[2 * kHid + i] = params[L.b3 + i];
+    }
+    if (threadIdx.x == 0) bias[3 * kHid] = params[L.b4];
     __syncthreads();
     const int w = threadIdx.x / kWave, lane = lane_id();
     const int r = lane & 15, kq = (lane >> 4) * 4;
-    unsigned short* my = act + w * 16 * kHid;
     const int64_t ntile = (io.n + 15) / 16;
     for (int64_t tile = int64_t(blockIdx.x) * kPruneWaves + w; tile < ntile;
          tile += int64_t(gridDim.x) * kPruneWaves) {
-        const int64_t q0 = tile * 16;
-        // gather features of 16 tuples: lane handles tuple r, features kq.. in chunks
-        {
-            const int64_t q = q0 + r;
-            const bool ok = q < io.n;
-            // each of the 4 lane groups fills 12 of the 48 features
-            float f[12];
+        const int64_t q = tile * 16 + r;
+        const bool ok = q < io.n;
+        // features kb * 16 + kq + e of tuple r, as the first layer's B fragments
+        float f[12];
 #pragma unroll
-            for (int k = 0; k < 12; ++k) f[k] = 0.0f;
-            if (ok) {
-                const int j0 = io.q_x0[q], j3 = io.q_x3[q];
-                const int t1 = io.q_tris[2 * q], t2 = io.q_tris[2 * q + 1];
+        for (int k = 0; k < 12; ++k) f[k] = 0.0f;
+        if (ok) {
+            const int j0 = io.q_x0[q], j3 = io.q_x3[q];
+            const int t1 = io.q_tris[2 * q], t2 = io.q_tris[2 * q + 1];
 #pragma unroll
-                for (int k = 0; k < 12; ++k) {
-                    const int fi = (lane >> 4) * 12 + k;
-                    float val = 0.0f;
-                    if (fi < 3) val = float((fi == 0 ? io.x0x[j0] : fi == 1 ? io.x0y[j0] : io.x0z[j0]) * 0.5);
-                    else if (fi < 6) val = float((fi == 3 ? io.x3x[j3] : fi == 4 ? io.x3y[j3] : io.x3z[j3]) * 0.5);
-                    else if (fi < 42) {
-                        const int g = (fi - 6) / 9, rem = (fi - 6) % 9, v = rem / 3, c = rem % 3;
-                        const int tt = (g == 0 || g == 2) ? t1 : t2;
-                        const int vid = io.tri[3 * tt + v];
-                        if (g < 2) val = float((c == 0 ? io.px[vid] : c == 1 ? io.py[vid] : io.pz[vid]) * 0.5);
-                        else val = float(c == 0 ? io.nx[vid] : c == 1 ? io.ny[vid] : io.nz[vid]);
-                    }
-                    f[k] = val;
+            for (int k = 0; k < 12; ++k) {
+                const int fi = (k >> 2) * 16 + kq + (k & 3);
+                float val = 0.0f;
+                if (fi < 3) val = float((fi == 0 ? io.x0x[j0] : fi == 1 ? io.x0y[j0] : io.x0z[j0]) * 0.5);
+                else if (fi < 6) val = float((fi == 3 ? io.x3x[j3] : fi == 4 ? io.x3y[j3] : io.x3z[j3]) * 0.5);
+                else if (fi < kIn) {
+                    const int g = (fi - 6) / 9, rem = (fi - 6) % 9, v = rem / 3, c = rem % 3;
+                    const int tt = (g == 0 || g == 2) ? t1 : t2;
+                    const int vid = io.tri[3 * tt + v];
+                    if (g < 2) val = float((c == 0 ? io.px[vid] : c == 1 ? io.py[vid] : io.pz[vid]) * 0.5);
+                    else val = float(c == 0 ? io.nx[vid] : c == 1 ? io.ny[vid] : io.nz[vid]);
                 }
+                f[k] = val;
             }
-#pragma unroll
-            for (int k = 0; k < 12; ++k) my[r * kFeat + (lane >> 4) * 12 + k] = f2bf(f[k]);
         }
-        __builtin_amdgcn_s_waitcnt(0);
-        __builtin_amdgcn_wave_barrier();
+        v4s x1[3];
+#pragma unroll
+        for (int kb = 0; kb < 3; ++kb) x1[kb] = frag4(f[4 * kb], f[4 * kb + 1], f[4 * kb + 2], f[4 * kb + 3]);
         v4f acc[8];
-        // layer 1
-        layer16<kFeat>(my, W1t, 8, acc);
-        __builtin_amdgcn_wave_barrier();
-#pragma unroll
-        for (int nt = 0; nt < 8; ++nt)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int col = nt * 16 + r, row = kq + e;
-                my[row * kHid + col] = f2bf(fmaxf(acc[nt][e] + params[L.b1 + col], 0.0f));
-            }
-        __builtin_amdgcn_s_waitcnt(0);
-        __builtin_amdgcn_wave_barrier();
-        layer16<kHid>(my, W2t, 8, acc);
-        __builtin_amdgcn_wave_barrier();
-#pragma unroll
-        for (int nt = 0; nt < 8; ++nt)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int col = nt * 16 + r, row = kq + e;
-                my[row * kHid + col] = f2bf(fmaxf(acc[nt][e] + params[L.b2 + col], 0.0f));
-            }
-        __builtin_amdgcn_s_waitcnt(0);
-        __builtin_amdgcn_wave_barrier();
-        layer16<kHid>(my, W3t, 8, acc);
-        __builtin_amdgcn_wave_barrier();
-#pragma unroll
-        for (int nt = 0; nt < 8; ++nt)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int col = nt * 16 + r, row = kq + e;
-                my[row * kHid + col] = f2bf(fmaxf(acc[nt][e] + params[L.b3 + col], 0.0f));
-            }
-        __builtin_amdgcn_s_waitcnt(0);
-        __builtin_amdgcn_wave_barrier();
-        layer16<kHid>(my, W4t, 1, acc);
-        // column 0 of the 16 x 16 result: lanes with (lane & 15) == 0 hold rows kq..kq+3
-        float z[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) z[e] = acc[0][e] + params[L.b4];
-        // broadcast: tuple row t = kq + e is held by lane (kq/4)*16 (r == 0)
-        float zr = 0.0f;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const float v = __shfl(z[e], ((lane & 15) >> 2) * 16, kWave);
-            if ((lane & 3) == e) zr = v;
-        }
-        // lanes 0..15 now hold tuple r's logit in zr (row = lane & 15)
-        const int64_t q = q0 + r;
-        const bool mine = lane < 16 && q < io.n;
+        v4s x[8];
+        layer_t<3, 8>(W1t, x1, acc);
+        relu_frags(acc, bias, x);
+        layer_t<8, 8>(W2t, x, acc);
+        relu_frags(acc, bias + kHid, x);
+        layer_t<8, 8>(W3t, x, acc);
+        relu_frags(acc, bias + 2 * kHid, x);
+        v4f out[1];
+        layer_t<8, 1>(W4t, x, out);
+        // lanes 0..15: row 0 of the output tile, the logit of tuple r
+        const float zr = out[0][0] + bias[3 * kHid];
+        const bool mine = lane < 16 && ok;
         const float p = 1.0f / (1.0f + expf(-zr));
         if (mine && scores) scores[q] = p;
         const bool keep = mine && p >= threshold;
@@ -377,7 +360,6 @@ __global__ void __launch_bounds__(kPruneWaves * 64) k_prune_score(PrunerIO io, c
                 if (o < (unsigned long long)cap) keep_idx[o] = int32_t(q);
             }
         }
-        __builtin_amdgcn_wave_barrier();
     }
 }
 
