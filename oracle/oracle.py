@@ -366,7 +366,7 @@ TAIL_DTYPE = np.dtype([("mask", np.int32), ("margin", np.float64), ("fresnel", n
 
 
 def tail(P, N, tri, x0s, xls, q_x0, q_xl, ptri, pu, pv, chain: str, eta, intensity=1.0, rho=1.0, teps=1e-6,
-         h=1e-5) -> np.ndarray:
+         h=1e-6) -> np.ndarray:
     """Visibility and contribution of n paths with k = len(chain) vertices.
     ptri, pu, pv: [n, k] triangle ids and barycentrics of x1..xk; q_x0, q_xl:
     receiver and light index per path; eta: k+1 indices (eta[i] between x_i

@@ -22,7 +22,8 @@
  *    vertex) and a constant reflectance rho at a reflection.  The oracle takes
  *    dA/dw from central differences of a forward trace from the light
  *    through the planes of the chain's triangles (shading normals
- *    interpolated at each hit) onto the receiver plane.
+ *    interpolated at each hit) onto the receiver plane, at two step sizes
+ *    combined by Richardson extrapolation.
  */
 #include <math.h>
 #include <omp.h>
@@ -243,10 +244,15 @@ int ot_tail(const double *P, const double *N, const int32_t *tri, int64_t nt, co
         basis(R.wl, &R.ea, &R.eb);
         R.x0 = x[0]; R.w0 = tnorm(tsub(x[1], x[0]));
         basis(R.w0, &R.fa, &R.fb);
+        /* central differences at steps h and h/4, combined by Richardson
+         * extrapolation (their error is c h^2 + O(h^4)); the change from the
+         * h/4 value to the extrapolated one is the error estimate reported */
         double a1, a2;
         if (area_per_solid_angle(&R, h, &a1) && area_per_solid_angle(&R, 0.25 * h, &a2) && a1 > 0 && a2 > 0) {
-            E[p] = intensity * F / a1;
-            E_change[p] = fabs(a1 - a2) / a2;
+            double ar = (16.0 * a2 - a1) / 15.0;
+            if (!(ar > 0)) ar = a2;
+            E[p] = intensity * F / ar;
+            E_change[p] = fabs(a2 - ar) / ar;
         } else {
             E[p] = 0.0;
             E_change[p] = INFINITY;
