@@ -317,6 +317,17 @@ def main():
 
 
 TAIL_BYTES = 56 + 8 + 4 + 8 + 8  # per path: record, two query ids, mask, contribution, image add
+# HBM bytes per reflection path of k_tail<1> on the glints workload (FETCH_SIZE x2.0 + WRITE_SIZE x1.0,
+# KiB per dispatch over 8,824,972 paths; profiles/tail_glints_hbm_counters.md), under a check of the
+# tail's own sources
+TRAFFIC_TAIL = {"sha": "e96dd6205077e27e", "paths": 8824972, "fetch_kib": 412944.4, "write_kib": 185462.75}
+
+
+def tail_traffic(paths: int):
+    t = TRAFFIC_TAIL
+    if _kernel_sha(("tail.hip", "tail.hpp")) != t["sha"]:
+        return None
+    return (t["fetch_kib"] * 2.0 + t["write_kib"]) * 1024.0 / t["paths"] * paths
 
 
 def tail_leg(ctx, spoly, dm, pts, dl, buf, reps: int = 5):
@@ -365,6 +376,7 @@ def tail_leg(ctx, spoly, dm, pts, dl, buf, reps: int = 5):
                    "kernel": f"k_tail<1> ({ev})",
                    "roofline": {"bound": "hbm", "achieved": gbps, "peak": PEAK_HBM, "unit": "GB/s",
                                 "frac": gbps / PEAK_HBM, "algorithmic_bytes_per_path": TAIL_BYTES,
+                                "traffic": tail_traffic(n) if ev == "R" else None,
                                 "note": "the BVH, mesh and endpoints stay in L2/MALL; the kernel is bound by "
                                         "dependent node loads of the traversal, not by HBM"}}
         tot_paths += n
@@ -460,7 +472,7 @@ def mixed_leg(args, ctx):
         ctx.solve_mixed(m1, *p1, *q1, "R", 1.0, 1.0, m2, r2, l2, Q2.q0, Q2.q3, Q2.qt, precision=prec, shape=shape,
                         out=out, out_count=cnt, queue=queue, sync=False)
 
-    cand = {"workgroups_per_cu": (1, 2, 4), "r_tile": (256, 1024), "order": (0, 2)}
+    cand = {"workgroups_per_cu": (1, 2, 4, 8), "r_tile": (256, 1024), "order": (0, 2)}
     key = autotune.signature(len(i1), len(i2), "R", prec)
     best, timings, cached = autotune.tune(launch, key, reps=1, candidates=cand)
     print(f"[bench] mixed autotune best {best.workgroups_per_cu}/{best.r_tile}/{best.order} "
