@@ -180,7 +180,8 @@ spoly_status spoly_cull_1bounce(spoly_ctx *ctx, const spoly_mesh *mesh,
  * zeroed by the caller) the total number found.
  * counters (optional, device uint64 [4], accumulated): [0] real roots of r(v)
  * found in [0,1], [1] (u,v) candidates polished, [2] degenerate instances,
- * [3] reserved.
+ * [3] valid solutions dropped because an instance had more than four (each
+ * instance keeps at most four; nonzero means some instance lost solutions).
  * diag_q (optional, device int32 [2*n_queries]): per query the number of roots
  * of r(v) in [0,1] and the number of solutions.
  * Runs in two phases: the front finds the roots of r(v) and lists the

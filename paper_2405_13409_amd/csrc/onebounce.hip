@@ -294,6 +294,7 @@ __device__ __forceinline__ bool vertex_law(V3<double> xp, V3<double> x, V3<doubl
 struct LaneSols {
     double u[kMaxLaneSol], v[kMaxLaneSol], res[kMaxLaneSol], edge[kMaxLaneSol];
     int n;
+    int over;  // solutions past the kMaxLaneSol kept (counted, not written)
 };
 
 __device__ __forceinline__ void push_sol(LaneSols& S, double u, double v, double res, double edge, double dedup)
@@ -312,6 +313,7 @@ __device__ __forceinline__ void push_sol(LaneSols& S, double u, double v, double
             S.edge[k] = edge;
         }
     if (S.n < kMaxLaneSol) S.n++;
+    else S.over++;
 }
 
 // Coefficients and elimination: r(v), normalised.  Returns false for a
@@ -669,10 +671,12 @@ __device__ __forceinline__ void emit_lane(const OneBounceArgs& A, int64_t q, boo
         unsigned long long s0 = wave_sum_u64(active ? nvr : 0);
         unsigned long long s1 = wave_sum_u64(active ? ncand : 0);
         unsigned long long s2 = wave_sum_u64(active ? degen : 0);
+        unsigned long long s3 = wave_sum_u64(active ? S.over : 0);
         if (lane_id() == 0) {
             if (s0) atomicAdd(A.counters + 0, s0);
             if (s1) atomicAdd(A.counters + 1, s1);
             if (s2) atomicAdd(A.counters + 2, s2);
+            if (s3) atomicAdd(A.counters + 3, s3);
         }
     }
     if (A.diag_q && active) {
@@ -691,6 +695,7 @@ __device__ __forceinline__ void onebounce_lane(const OneBounceArgs& A, int64_t q
 {
     LaneSols S;
     S.n = 0;
+    S.over = 0;
     int nvr = 0, ncand = 0, degen = 0;
     int tid = -1;
     bool swapped = false;
@@ -974,6 +979,7 @@ __global__ void __launch_bounds__(256) k_ob_back(OneBounceArgs A)
         const bool active = i < n_items;
         LaneSols S;
         S.n = 0;
+        S.over = 0;
         int ncand = 0, tid = -1;
         bool swapped = false, defer = false;
         int64_t q = 0;
@@ -999,6 +1005,7 @@ __global__ void __launch_bounds__(256) k_ob_back(OneBounceArgs A)
                 // the waves here do not wait for the refinement of few lanes.
                 defer = true;
                 S.n = 0;
+                S.over = 0;
                 ncand = 0;
             }
         }
@@ -1024,6 +1031,7 @@ __global__ void __launch_bounds__(256) k_ob_full(OneBounceArgs A)
         const bool active = i < n_full;
         LaneSols S;
         S.n = 0;
+        S.over = 0;
         int ncand = 0, tid = -1, nv = 0, dg = 0;
         bool swapped = false;
         int64_t q = 0;

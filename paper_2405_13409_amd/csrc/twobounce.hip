@@ -775,6 +775,7 @@ __device__ __forceinline__ void tt_tuple(const TTArgs& A, int64_t q, double* lds
     // validation) for the final midpoint of every sign-change piece.
     LaneTT S;
     S.n = 0;
+    S.over = 0;
     int ncand = 0;
     auto path_phase = [&](const double v) {
         double c[kDA + 1];
@@ -805,7 +806,11 @@ __device__ __forceinline__ void tt_tuple(const TTArgs& A, int64_t q, double* lds
 #pragma unroll
             for (int q2 = 0; q2 < kTTMaxSol; ++q2)
                 if (q2 < S.n && fabs(S.u1[q2] - u) < A.dedup && fabs(S.v1[q2] - vv) < A.dedup) dup = true;
-            if (dup || S.n >= kTTMaxSol) continue;
+            if (dup) continue;
+            if (S.n >= kTTMaxSol) {
+                S.over++;
+                continue;
+            }
 #pragma unroll
             for (int q2 = 0; q2 < kTTMaxSol; ++q2)
                 if (q2 == S.n) {
@@ -952,7 +957,9 @@ __device__ __forceinline__ void tt_tuple(const TTArgs& A, int64_t q, double* lds
     }
     if (A.counters) {
         unsigned long long c1 = wave_sum_u64(ncand);
+        unsigned long long c3 = wave_sum_u64(S.over);
         if (lane == 0) {
+            if (c3) atomicAdd(A.counters + 3, c3);
             if (nv) atomicAdd(A.counters + 0, (unsigned long long)nv);
             if (c1) atomicAdd(A.counters + 1, c1);
             if (degen) atomicAdd(A.counters + 2, 1ull);

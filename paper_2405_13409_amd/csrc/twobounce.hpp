@@ -33,6 +33,7 @@ constexpr int kMaxBisect = 40;                   // bisection steps per sign cha
 struct LaneTT {
     double u1[4], v1[4], u2[4], v2[4], res[4], edge[4];
     int n;
+    int over;  // valid paths past the four kept (counted, not written)
 };
 
 hipError_t launch_tt_solve(const TTArgs& A, hipStream_t stream);

@@ -51,6 +51,7 @@ def test_small_glints_reflection_parity(sp, ctx, prec):
     assert st["compared"] > 50
     assert st["ambiguous_fraction"] < 0.01
     assert cnt[2] == 0  # no degenerate instance
+    assert cnt[3] == 0  # no instance with more solutions than the four kept
 
 
 @pytest.mark.parametrize("prec", [0, 1])

@@ -78,6 +78,7 @@ def test_tt_traced_paths_parity(sp, ctx):
     g, cnt = _gpu_tt(sp, ctx, mesh, x0s, x3, q0, z, qt)
     n, nb = _compare_tt(g, o, len(q0))
     print("tt compared", n, "excluded", nb, "oracle sign changes", od["n_vroots"].sum(), "gpu", cnt[0])
+    assert cnt[3] == 0  # no tuple with more paths than the four kept
     assert n >= 3
 
 
