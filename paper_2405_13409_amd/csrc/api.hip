@@ -34,6 +34,8 @@ struct spoly_ctx {
     int stage_n;             // kernels timed by stage_ev (0: none yet)
     void* ord_block;         // workspace of SPOLY_FLAG_DETERMINISTIC_ORDER, grown on demand
     size_t ord_bytes;
+    float* tri_feat;         // pruner scorer: per-triangle feature rows, grown on demand
+    int64_t tri_feat_cap;    // in triangles
 };
 
 namespace {
@@ -131,6 +133,7 @@ void spoly_ctx_destroy(spoly_ctx* ctx)
     if (ctx->ob_block) (void)hipFree(ctx->ob_block);
     if (ctx->ob_rblock) (void)hipFree(ctx->ob_rblock);
     if (ctx->ord_block) (void)hipFree(ctx->ord_block);
+    if (ctx->tri_feat) (void)hipFree(ctx->tri_feat);
     if (ctx->stage_ev[0])
         for (int i = 0; i < 5; ++i) (void)hipEventDestroy(ctx->stage_ev[i]);
     std::free(ctx);
@@ -558,8 +561,16 @@ spoly_status spoly_prune_score(spoly_ctx* ctx, const spoly_mesh* mesh, const spo
     if (!fill_io(io, mesh, x0s, x3s, q_x0, q_x3, q_tris, n)) return SPOLY_E_INVALID_ARG;
     if (!(threshold >= 0.0f) || !(threshold <= 1.0f)) return SPOLY_E_INVALID_ARG;
     if (hipSetDevice(ctx->device) != hipSuccess) return SPOLY_E_DEVICE;
+    if (ctx->tri_feat_cap < mesh->n_tris) {
+        if (ctx->tri_feat) (void)hipFree(ctx->tri_feat);
+        ctx->tri_feat = nullptr;
+        ctx->tri_feat_cap = 0;
+        if (hipMalloc(&ctx->tri_feat, sizeof(float) * spoly::kTriFeat * size_t(mesh->n_tris)) != hipSuccess)
+            return SPOLY_E_DEVICE;
+        ctx->tri_feat_cap = mesh->n_tris;
+    }
     return dev_err(spoly::launch_prune_score(io, params, threshold, scores, keep_idx, keep_capacity, keep_count,
-                                             static_cast<hipStream_t>(stream)));
+                                             ctx->tri_feat, mesh->n_tris, static_cast<hipStream_t>(stream)));
 }
 
 spoly_status spoly_pruner_fwd_bwd(spoly_ctx* ctx, const spoly_mesh* mesh, const spoly_points* x0s,

@@ -219,7 +219,12 @@ __global__ void k_adam(float* p, const float* g, float* m, float* v, int64_t n, 
 // [out][in] so that a lane's four consecutive k of an A fragment are one
 // 8-byte read; the output layer's row 0 leaves each tuple's logit in lanes
 // 0..15.
-constexpr int kW1 = kHid * kFeat, kW2 = kHid * kHid, kW4 = 16 * kHid;
+// Weight rows are padded by 8 bf16 (16 bytes): with 128 bf16 per row the 16
+// rows a half-wave reads at one k offset would sit 256 bytes apart, all in one
+// LDS bank; padded, the 32 eight-byte reads of a half-wave fall in distinct
+// banks.
+constexpr int kS1 = kFeat + 8, kS2 = kHid + 8;
+constexpr int kW1 = kHid * kS1, kW2 = kHid * kS2, kW4 = 16 * kS2;
 constexpr int kPruneWaves = 12;
 constexpr int kPruneLds = (kW1 + 2 * kW2 + kW4) * 2 + 4 * kHid * 4;
 
@@ -237,8 +242,8 @@ __device__ __forceinline__ v4s frag4(float a, float b, float c, float d)
     return __builtin_bit_cast(v4s, u);
 }
 
-template <int KB, int NT>
-__device__ __forceinline__ void layer_t(const unsigned short* wt /*[NT*16][KB*16]*/, const v4s (&x)[KB],
+template <int KB, int NT, int LD>
+__device__ __forceinline__ void layer_t(const unsigned short* wt /*[NT*16][LD], LD >= KB*16*/, const v4s (&x)[KB],
                                         v4f (&acc)[NT])
 {
     const int lane = lane_id(), r = lane & 15, kq = (lane >> 4) * 4;
@@ -248,7 +253,7 @@ __device__ __forceinline__ void layer_t(const unsigned short* wt /*[NT*16][KB*16
     for (int kb = 0; kb < KB; ++kb) {
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
-            const v4s w = *reinterpret_cast<const v4s*>(wt + (nt * 16 + r) * (KB * 16) + kb * 16 + kq);
+            const v4s w = *reinterpret_cast<const v4s*>(wt + (nt * 16 + r) * LD + kb * 16 + kq);
             acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w, x[kb], acc[nt], 0, 0, 0);
         }
         // keep the weight reads of one k-block in flight at a time (the
@@ -269,29 +274,52 @@ __device__ __forceinline__ void relu_frags(const v4f (&acc)[8], const float* bia
     }
 }
 
-__global__ void __launch_bounds__(kPruneWaves * 64) k_prune_score(PrunerIO io, const float* params, float threshold,
-                                                                float* scores, int32_t* keep_idx, int64_t cap,
-                                                                unsigned long long* keep_count)
+// Per-triangle feature rows: the three positions divided by 2, then the three
+// vertex normals, as the scorer's features take them (rounded from double
+// exactly as the training gather does), so that a tuple's features come from
+// two rows instead of six vertex lookups.
+__global__ void k_tri_feat(PrunerIO io, int32_t n_tris, float* tf)
+{
+    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tris) return;
+    float* row = tf + size_t(t) * kTriFeat;
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+        const int vid = io.tri[3 * t + v];
+        row[3 * v + 0] = float(io.px[vid] * 0.5);
+        row[3 * v + 1] = float(io.py[vid] * 0.5);
+        row[3 * v + 2] = float(io.pz[vid] * 0.5);
+        row[9 + 3 * v + 0] = float(io.nx[vid]);
+        row[9 + 3 * v + 1] = float(io.ny[vid]);
+        row[9 + 3 * v + 2] = float(io.nz[vid]);
+    }
+    row[18] = 0.0f;
+    row[19] = 0.0f;
+}
+
+__global__ void __launch_bounds__(kPruneWaves * 64) k_prune_score(PrunerIO io, const float* tf, const float* params,
+                                                                float threshold, float* scores, int32_t* keep_idx,
+                                                                int64_t cap, unsigned long long* keep_count)
 {
     extern __shared__ unsigned short sm[];
-    unsigned short* W1t = sm;              // [128][48]
-    unsigned short* W2t = W1t + kW1;       // [128][128]
+    unsigned short* W1t = sm;              // [128][kS1]
+    unsigned short* W2t = W1t + kW1;       // [128][kS2]
     unsigned short* W3t = W2t + kW2;
-    unsigned short* W4t = W3t + kW2;       // [16][128], row 0 real
+    unsigned short* W4t = W3t + kW2;       // [16][kS2], row 0 real
     float* bias = reinterpret_cast<float*>(W4t + kW4);   // b1, b2, b3 [128 each], b4
     const PrunerLayout L;
     for (int i = threadIdx.x; i < kW1; i += blockDim.x) {
-        const int o = i / kFeat, k = i % kFeat;
+        const int o = i / kS1, k = i % kS1;
         W1t[i] = k < kIn ? f2bf(params[L.w1 + k * kHid + o]) : (unsigned short)0;
     }
     for (int i = threadIdx.x; i < kW2; i += blockDim.x) {
-        const int o = i / kHid, k = i % kHid;
-        W2t[i] = f2bf(params[L.w2 + k * kHid + o]);
-        W3t[i] = f2bf(params[L.w3 + k * kHid + o]);
+        const int o = i / kS2, k = i % kS2;
+        W2t[i] = k < kHid ? f2bf(params[L.w2 + k * kHid + o]) : (unsigned short)0;
+        W3t[i] = k < kHid ? f2bf(params[L.w3 + k * kHid + o]) : (unsigned short)0;
     }
     for (int i = threadIdx.x; i < kW4; i += blockDim.x) {
-        const int o = i / kHid, k = i % kHid;
-        W4t[i] = o == 0 ? f2bf(params[L.w4 + k]) : (unsigned short)0;
+        const int o = i / kS2, k = i % kS2;
+        W4t[i] = (o == 0 && k < kHid) ? f2bf(params[L.w4 + k]) : (unsigned short)0;
     }
     for (int i = threadIdx.x; i < kHid; i += blockDim.x) {
         bias[i] = params[L.b1 + i];
@@ -303,46 +331,68 @@ __global__ void __launch_bounds__(kPruneWaves * 64) k_prune_score(PrunerIO io, c
     const int w = threadIdx.x / kWave, lane = lane_id();
     const int r = lane & 15, kq = (lane >> 4) * 4;
     const int64_t ntile = (io.n + 15) / 16;
-    for (int64_t tile = int64_t(blockIdx.x) * kPruneWaves + w; tile < ntile;
-         tile += int64_t(gridDim.x) * kPruneWaves) {
+    const int64_t stride = int64_t(gridDim.x) * kPruneWaves;
+    // Software pipeline over this wave's tiles: the tuple ids of tile i+2 and
+    // the feature rows of tile i+1 are requested before tile i's layers run,
+    // so their latency overlaps the matrix work.
+    struct Ids {
+        int j0, j3, t1, t2;
+        bool ok;
+    };
+    auto load_ids = [&](int64_t tile) {
+        Ids d{0, 0, 0, 0, false};
+        const int64_t q = tile * 16 + r;
+        if (tile < ntile && q < io.n) {
+            d.j0 = io.q_x0[q];
+            d.j3 = io.q_x3[q];
+            d.t1 = io.q_tris[2 * q];
+            d.t2 = io.q_tris[2 * q + 1];
+            d.ok = true;
+        }
+        return d;
+    };
+    // features kb * 16 + kq + e of the lane's tuple: x0/2, x3/2, T1 positions,
+    // T2 positions, T1 normals, T2 normals (zero past the 42nd)
+    auto load_feats = [&](const Ids& d, float (&f)[12]) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            const int fi = (k >> 2) * 16 + kq + (k & 3);
+            float val = 0.0f;
+            if (d.ok) {
+                if (fi < 3) val = float((fi == 0 ? io.x0x[d.j0] : fi == 1 ? io.x0y[d.j0] : io.x0z[d.j0]) * 0.5);
+                else if (fi < 6) val = float((fi == 3 ? io.x3x[d.j3] : fi == 4 ? io.x3y[d.j3] : io.x3z[d.j3]) * 0.5);
+                else if (fi < kIn) {
+                    const int g = (fi - 6) / 9, rem = (fi - 6) % 9;
+                    const int tt = (g == 0 || g == 2) ? d.t1 : d.t2;
+                    val = tf[size_t(tt) * kTriFeat + (g >= 2 ? 9 : 0) + rem];
+                }
+            }
+            f[k] = val;
+        }
+    };
+    int64_t tile = int64_t(blockIdx.x) * kPruneWaves + w;
+    float f[12];
+    load_feats(load_ids(tile), f);
+    Ids next = load_ids(tile + stride);
+    for (; tile < ntile; tile += stride) {
         const int64_t q = tile * 16 + r;
         const bool ok = q < io.n;
-        // features kb * 16 + kq + e of tuple r, as the first layer's B fragments
-        float f[12];
-#pragma unroll
-        for (int k = 0; k < 12; ++k) f[k] = 0.0f;
-        if (ok) {
-            const int j0 = io.q_x0[q], j3 = io.q_x3[q];
-            const int t1 = io.q_tris[2 * q], t2 = io.q_tris[2 * q + 1];
-#pragma unroll
-            for (int k = 0; k < 12; ++k) {
-                const int fi = (k >> 2) * 16 + kq + (k & 3);
-                float val = 0.0f;
-                if (fi < 3) val = float((fi == 0 ? io.x0x[j0] : fi == 1 ? io.x0y[j0] : io.x0z[j0]) * 0.5);
-                else if (fi < 6) val = float((fi == 3 ? io.x3x[j3] : fi == 4 ? io.x3y[j3] : io.x3z[j3]) * 0.5);
-                else if (fi < kIn) {
-                    const int g = (fi - 6) / 9, rem = (fi - 6) % 9, v = rem / 3, c = rem % 3;
-                    const int tt = (g == 0 || g == 2) ? t1 : t2;
-                    const int vid = io.tri[3 * tt + v];
-                    if (g < 2) val = float((c == 0 ? io.px[vid] : c == 1 ? io.py[vid] : io.pz[vid]) * 0.5);
-                    else val = float(c == 0 ? io.nx[vid] : c == 1 ? io.ny[vid] : io.nz[vid]);
-                }
-                f[k] = val;
-            }
-        }
+        float fn[12];
+        load_feats(next, fn);
+        next = load_ids(tile + 2 * stride);
         v4s x1[3];
 #pragma unroll
         for (int kb = 0; kb < 3; ++kb) x1[kb] = frag4(f[4 * kb], f[4 * kb + 1], f[4 * kb + 2], f[4 * kb + 3]);
         v4f acc[8];
         v4s x[8];
-        layer_t<3, 8>(W1t, x1, acc);
+        layer_t<3, 8, kS1>(W1t, x1, acc);
         relu_frags(acc, bias, x);
-        layer_t<8, 8>(W2t, x, acc);
+        layer_t<8, 8, kS2>(W2t, x, acc);
         relu_frags(acc, bias + kHid, x);
-        layer_t<8, 8>(W3t, x, acc);
+        layer_t<8, 8, kS2>(W3t, x, acc);
         relu_frags(acc, bias + 2 * kHid, x);
         v4f out[1];
-        layer_t<8, 1>(W4t, x, out);
+        layer_t<8, 1, kS2>(W4t, x, out);
         // lanes 0..15: row 0 of the output tile, the logit of tuple r
         const float zr = out[0][0] + bias[3 * kHid];
         const bool mine = lane < 16 && ok;
@@ -360,6 +410,8 @@ __global__ void __launch_bounds__(kPruneWaves * 64) k_prune_score(PrunerIO io, c
                 if (o < (unsigned long long)cap) keep_idx[o] = int32_t(q);
             }
         }
+#pragma unroll
+        for (int k = 0; k < 12; ++k) f[k] = fn[k];
     }
 }
 
@@ -374,7 +426,8 @@ hipError_t launch_gather(const PrunerIO& io, unsigned short* X, float* Xf, hipSt
 }
 
 hipError_t launch_prune_score(const PrunerIO& io, const float* params, float threshold, float* scores,
-                              int32_t* keep_idx, int64_t cap, unsigned long long* keep_count, hipStream_t s)
+                              int32_t* keep_idx, int64_t cap, unsigned long long* keep_count, float* tri_feat,
+                              int32_t n_tris, hipStream_t s)
 {
     if (io.n <= 0) return hipSuccess;
     static bool attr = false;
@@ -382,6 +435,7 @@ hipError_t launch_prune_score(const PrunerIO& io, const float* params, float thr
         (void)hipFuncSetAttribute((const void*)k_prune_score, hipFuncAttributeMaxDynamicSharedMemorySize, kPruneLds);
         attr = true;
     }
+    k_tri_feat<<<nblk(n_tris, 256), 256, 0, s>>>(io, n_tris, tri_feat);
     // persistent: one block per compute unit (its LDS allows no second), each
     // loading the weights once and striding over 16-tuple tiles
     int dev = 0, cus = 0;
@@ -391,8 +445,8 @@ hipError_t launch_prune_score(const PrunerIO& io, const float* params, float thr
     const int64_t tiles = (io.n + 15) / 16;
     int64_t blocks = (tiles + kPruneWaves - 1) / kPruneWaves;
     if (blocks > cus) blocks = cus;
-    hipLaunchKernelGGL(k_prune_score, dim3(unsigned(blocks)), dim3(kPruneWaves * 64), kPruneLds, s, io, params,
-                       threshold, scores, keep_idx, cap, keep_count);
+    hipLaunchKernelGGL(k_prune_score, dim3(unsigned(blocks)), dim3(kPruneWaves * 64), kPruneLds, s, io, tri_feat,
+                       params, threshold, scores, keep_idx, cap, keep_count);
     return hipGetLastError();
 }
 

@@ -50,8 +50,12 @@ struct PrunerWork {   // per-batch activations (device), sized for `cap` tuples
 
 hipError_t launch_gemm(const GemmArgs& G, int split_k, hipStream_t stream);
 hipError_t launch_gather(const PrunerIO& io, unsigned short* X, float* Xf, hipStream_t s);
+// Scores (and keeps) n tuples; tri_feat: device workspace of kTriFeat floats
+// per triangle of the mesh (n_tris), filled by the call.
+constexpr int kTriFeat = 20;
 hipError_t launch_prune_score(const PrunerIO& io, const float* params, float threshold, float* scores,
-                              int32_t* keep_idx, int64_t cap, unsigned long long* keep_count, hipStream_t s);
+                              int32_t* keep_idx, int64_t cap, unsigned long long* keep_count, float* tri_feat,
+                              int32_t n_tris, hipStream_t s);
 hipError_t pruner_fwd_bwd(const PrunerIO& io, const float* labels, float pos_w, const float* params, float* grads,
                           float* loss, PrunerWork& W, hipStream_t s);
 hipError_t pruner_adam(float* p, const float* g, float* m, float* v, int64_t step, float lr, float b1, float b2,

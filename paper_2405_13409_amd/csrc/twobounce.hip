@@ -629,7 +629,8 @@ __device__ int tt_det_sign(const TTGeo& g, const double* __restrict__ Ac, int da
         c[k] *= pw;
         pw *= B;
     }
-    return ma <= 8 ? sign_over_roots<8>(g, c, B, v) : sign_over_roots<kDA>(g, c, B, v);
+    if (ma <= 8) return sign_over_roots<8>(g, c, B, v);
+    return ma <= 13 ? sign_over_roots<13>(g, c, B, v) : sign_over_roots<kDA>(g, c, B, v);
 }
 
 // ------------------------------------------------------------------ path phase (exact constraints, FP64)
