@@ -2,7 +2,8 @@
 // (ReLU, sigmoid) scores each (x0, T1, T2, x3) tuple from the separators and
 // the positions / normals of both triangles; tuples scoring below a
 // calibrated threshold are not sent to the solver.  Dense layers run on the
-// matrix cores: bf16 operands, fp32 accumulation (v_mfma_f32_16x16x16_bf16).
+// matrix cores: bf16 operands, fp32 accumulation (v_mfma_f32_16x16x32_bf16 in
+// the scorer, v_mfma_f32_16x16x16_bf16 in the training GEMM).
 //   training : k_gather -> 4 x (GEMM, bias/ReLU) -> loss gradient -> backward
 //              GEMMs (split-K for weight gradients) -> Adam
 //   inference: one fused kernel, weights staged in LDS, 16 tuples per wave tile.
@@ -212,24 +213,30 @@ __global__ void k_adam(float* p, const float* g, float* m, float* v, int64_t n, 
 // ------------------------------------------------------------------ fused inference
 // One 16-tuple tile per wave, activations kept in registers: every layer
 // computes H^T = W^T X^T on the matrix cores (weights as the A operand, the
-// tile's activations as B).  Its D fragment -- lane l holds tuple l & 15 and
-// four consecutive output neurons 4 (l >> 4) .. + 3 of each 16-neuron tile --
-// is then exactly the B fragment of the next layer's 16-neuron k-block, so no
-// activation goes through LDS.  Weights and biases sit in LDS, transposed to
-// [out][in] so that a lane's four consecutive k of an A fragment are one
-// 8-byte read; the output layer's row 0 leaves each tuple's logit in lanes
+// tile's activations as B), 32 inputs per instruction.  A 16x16 D fragment
+// leaves lane l with tuple l & 15 and output neurons 4 (l >> 4) .. + 3 of its
+// 16-neuron tile; the two D fragments of neurons 32c .. 32c + 31 together give
+// each lane the eight values the next layer's B fragment of k-chunk c needs,
+// if that layer's weight columns are stored in the matching order (kperm), so
+// no activation goes through LDS.  The k order inside an instruction does not
+// matter to the sum as long as A and B agree on it, which they do: both take
+// a lane's eight values in the same slots.  Weights and biases sit in LDS,
+// transposed to [out][in] so that a lane's eight k of an A fragment are one
+// 16-byte read; the output layer's row 0 leaves each tuple's logit in lanes
 // 0..15.
 // Weight rows are padded by 8 bf16 (16 bytes): with 128 bf16 per row the 16
-// rows a half-wave reads at one k offset would sit 256 bytes apart, all in one
-// LDS bank; padded, the 32 eight-byte reads of a half-wave fall in distinct
-// banks.
+// rows a quarter-wave reads at one k offset would sit 256 bytes apart, all in
+// the same LDS banks; padded, the reads of a quarter-wave cover all 64 banks
+// once.
 constexpr int kS1 = kFeat + 8, kS2 = kHid + 8;
 constexpr int kW1 = kHid * kS1, kW2 = kHid * kS2, kW4 = 16 * kS2;
 constexpr int kPruneWaves = 12;
 constexpr int kPruneLds = (kW1 + 2 * kW2 + kW4) * 2 + 4 * kHid * 4;
 
 typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 typedef float f2v __attribute__((ext_vector_type(2)));
+typedef float f8v __attribute__((ext_vector_type(8)));
 
 // four floats as a bf16 fragment (round to nearest even, native conversion)
 __device__ __forceinline__ v4s frag4(float a, float b, float c, float d)
@@ -242,35 +249,50 @@ __device__ __forceinline__ v4s frag4(float a, float b, float c, float d)
     return __builtin_bit_cast(v4s, u);
 }
 
-template <int KB, int NT, int LD>
-__device__ __forceinline__ void layer_t(const unsigned short* wt /*[NT*16][LD], LD >= KB*16*/, const v4s (&x)[KB],
+// Storage slot -> hidden neuron of a weight row whose inputs are the previous
+// layer's activations: slot 32c + 8g + p holds neuron 32c + 4g + (p & 3) +
+// 16 (p >> 2), the neuron a lane of group g holds in element p of its k-chunk
+// c fragment (elements 0..3 from D tile 2c, 4..7 from D tile 2c + 1).
+__device__ __forceinline__ int kperm(int slot)
+{
+    const int c = slot >> 5, g = (slot >> 3) & 3, p = slot & 7;
+    return 32 * c + 4 * g + (p & 3) + 16 * (p >> 2);
+}
+
+template <int KC, int NT, int LD>
+__device__ __forceinline__ void layer32(const unsigned short* wt /*[NT*16][LD], LD >= KC*32*/, const bf8v (&x)[KC],
                                         v4f (&acc)[NT])
 {
-    const int lane = lane_id(), r = lane & 15, kq = (lane >> 4) * 4;
+    const int lane = lane_id(), r = lane & 15, k8 = (lane >> 4) * 8;
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) acc[nt] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int kb = 0; kb < KB; ++kb) {
+    for (int c = 0; c < KC; ++c) {
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
-            const v4s w = *reinterpret_cast<const v4s*>(wt + (nt * 16 + r) * LD + kb * 16 + kq);
-            acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w, x[kb], acc[nt], 0, 0, 0);
+            const bf8v w = *reinterpret_cast<const bf8v*>(wt + (nt * 16 + r) * LD + c * 32 + k8);
+            acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, x[c], acc[nt], 0, 0, 0);
         }
-        // keep the weight reads of one k-block in flight at a time (the
+        // keep the weight reads of one k-chunk in flight at a time (the
         // scheduler would otherwise hoist a whole layer's and spill)
         __builtin_amdgcn_sched_barrier(0);
     }
 }
 
-// bias + ReLU of the eight output tiles, as the next layer's B fragments
-__device__ __forceinline__ void relu_frags(const v4f (&acc)[8], const float* bias, v4s (&x)[8])
+// bias + ReLU of the eight output tiles, as the next layer's four B fragments
+__device__ __forceinline__ void relu_frags(const v4f (&acc)[8], const float* bias, bf8v (&x)[4])
 {
     const int kq = (lane_id() >> 4) * 4;
 #pragma unroll
-    for (int nt = 0; nt < 8; ++nt) {
-        const float* bb = bias + nt * 16 + kq;
-        x[nt] = frag4(fmaxf(acc[nt][0] + bb[0], 0.f), fmaxf(acc[nt][1] + bb[1], 0.f),
-                      fmaxf(acc[nt][2] + bb[2], 0.f), fmaxf(acc[nt][3] + bb[3], 0.f));
+    for (int c = 0; c < 4; ++c) {
+        const float* b0 = bias + 32 * c + kq;
+        const float* b1 = b0 + 16;
+        const v4f& a0 = acc[2 * c];
+        const v4f& a1 = acc[2 * c + 1];
+        const f8v v = {fmaxf(a0[0] + b0[0], 0.f), fmaxf(a0[1] + b0[1], 0.f), fmaxf(a0[2] + b0[2], 0.f),
+                       fmaxf(a0[3] + b0[3], 0.f), fmaxf(a1[0] + b1[0], 0.f), fmaxf(a1[1] + b1[1], 0.f),
+                       fmaxf(a1[2] + b1[2], 0.f), fmaxf(a1[3] + b1[3], 0.f)};
+        x[c] = __builtin_convertvector(v, bf8v);
     }
 }
 
@@ -301,7 +323,7 @@ __global__ void __launch_bounds__(kPruneWaves * 64) k_prune_score(PrunerIO io, c
                                                                 float threshold, float* scores, int32_t* keep_idx,
                                                                 int64_t cap, unsigned long long* keep_count)
 {
-    extern __shared__ unsigned short sm[];
+    extern __shared__ __attribute__((aligned(16))) unsigned short sm[];
     unsigned short* W1t = sm;              // [128][kS1]
     unsigned short* W2t = W1t + kW1;       // [128][kS2]
     unsigned short* W3t = W2t + kW2;
@@ -314,12 +336,13 @@ __global__ void __launch_bounds__(kPruneWaves * 64) k_prune_score(PrunerIO io, c
     }
     for (int i = threadIdx.x; i < kW2; i += blockDim.x) {
         const int o = i / kS2, k = i % kS2;
-        W2t[i] = k < kHid ? f2bf(params[L.w2 + k * kHid + o]) : (unsigned short)0;
-        W3t[i] = k < kHid ? f2bf(params[L.w3 + k * kHid + o]) : (unsigned short)0;
+        const int h = k < kHid ? kperm(k) : 0;
+        W2t[i] = k < kHid ? f2bf(params[L.w2 + h * kHid + o]) : (unsigned short)0;
+        W3t[i] = k < kHid ? f2bf(params[L.w3 + h * kHid + o]) : (unsigned short)0;
     }
     for (int i = threadIdx.x; i < kW4; i += blockDim.x) {
         const int o = i / kS2, k = i % kS2;
-        W4t[i] = (o == 0 && k < kHid) ? f2bf(params[L.w4 + k]) : (unsigned short)0;
+        W4t[i] = (o == 0 && k < kHid) ? f2bf(params[L.w4 + kperm(k)]) : (unsigned short)0;
     }
     for (int i = threadIdx.x; i < kHid; i += blockDim.x) {
         bias[i] = params[L.b1 + i];
@@ -329,7 +352,7 @@ __global__ void __launch_bounds__(kPruneWaves * 64) k_prune_score(PrunerIO io, c
     if (threadIdx.x == 0) bias[3 * kHid] = params[L.b4];
     __syncthreads();
     const int w = threadIdx.x / kWave, lane = lane_id();
-    const int r = lane & 15, kq = (lane >> 4) * 4;
+    const int r = lane & 15, g = lane >> 4;
     const int64_t ntile = (io.n + 15) / 16;
     const int64_t stride = int64_t(gridDim.x) * kPruneWaves;
     // Software pipeline over this wave's tiles: the tuple ids of tile i+2 and
@@ -351,12 +374,13 @@ __global__ void __launch_bounds__(kPruneWaves * 64) k_prune_score(PrunerIO io, c
         }
         return d;
     };
-    // features kb * 16 + kq + e of the lane's tuple: x0/2, x3/2, T1 positions,
-    // T2 positions, T1 normals, T2 normals (zero past the 42nd)
+    // the lane's twelve features of its tuple -- 8g .. 8g + 7 for the 32-wide
+    // chunk, 32 + 4g .. + 3 for the 16-wide one -- out of x0/2, x3/2, T1
+    // positions, T2 positions, T1 normals, T2 normals (zero past the 42nd)
     auto load_feats = [&](const Ids& d, float (&f)[12]) {
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
-            const int fi = (k >> 2) * 16 + kq + (k & 3);
+            const int fi = k < 8 ? 8 * g + k : 32 + 4 * g + (k - 8);
             float val = 0.0f;
             if (d.ok) {
                 if (fi < 3) val = float((fi == 0 ? io.x0x[d.j0] : fi == 1 ? io.x0y[d.j0] : io.x0z[d.j0]) * 0.5);
@@ -380,19 +404,24 @@ __global__ void __launch_bounds__(kPruneWaves * 64) k_prune_score(PrunerIO io, c
         float fn[12];
         load_feats(next, fn);
         next = load_ids(tile + 2 * stride);
-        v4s x1[3];
-#pragma unroll
-        for (int kb = 0; kb < 3; ++kb) x1[kb] = frag4(f[4 * kb], f[4 * kb + 1], f[4 * kb + 2], f[4 * kb + 3]);
+        // first layer: inputs 0..31 in one 32-wide step, 32..47 in a 16-wide one
+        const bf8v x1a[1] = {__builtin_convertvector(((f8v){f[0], f[1], f[2], f[3], f[4], f[5], f[6], f[7]}), bf8v)};
+        const v4s x1b = frag4(f[8], f[9], f[10], f[11]);
         v4f acc[8];
-        v4s x[8];
-        layer_t<3, 8, kS1>(W1t, x1, acc);
+        layer32<1, 8, kS1>(W1t, x1a, acc);
+#pragma unroll
+        for (int nt = 0; nt < 8; ++nt) {
+            const v4s w = *reinterpret_cast<const v4s*>(W1t + (nt * 16 + r) * kS1 + 32 + 4 * g);
+            acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w, x1b, acc[nt], 0, 0, 0);
+        }
+        bf8v x[4];
         relu_frags(acc, bias, x);
-        layer_t<8, 8, kS2>(W2t, x, acc);
+        layer32<4, 8, kS2>(W2t, x, acc);
         relu_frags(acc, bias + kHid, x);
-        layer_t<8, 8, kS2>(W3t, x, acc);
+        layer32<4, 8, kS2>(W3t, x, acc);
         relu_frags(acc, bias + 2 * kHid, x);
         v4f out[1];
-        layer_t<8, 1, kS2>(W4t, x, out);
+        layer32<4, 1, kS2>(W4t, x, out);
         // lanes 0..15: row 0 of the output tile, the logit of tuple r
         const float zr = out[0][0] + bias[3 * kHid];
         const bool mine = lane < 16 && ok;

@@ -114,3 +114,46 @@ def test_adam_step_matches_reference(sp, ctx):
         vv = 0.999 * vv + 0.001 * g.astype(np.float64) ** 2
         pp = pp - 1e-3 * (mm / (1 - 0.9 ** step)) / (np.sqrt(vv / (1 - 0.999 ** step)) + 1e-8)
     assert np.max(np.abs(P.cpu().numpy() - pp)) < 1e-5
+
+
+def _bf16(a):
+    """Round to bfloat16 (nearest even) through float32, as the kernel does."""
+    return torch.from_numpy(np.asarray(a, dtype=np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+
+
+def _forward_bf16(p, X):
+    """FP64 twin forward with the kernel's roundings: inputs, weights and each
+    hidden layer's activations rounded to bf16; biases in float32."""
+    W = mlp.unpack(p)
+    b = {k: np.asarray(W[k], dtype=np.float32).astype(np.float64) for k in ("b1", "b2", "b3", "b4")}
+    h = _bf16(X)
+    for i in (1, 2, 3):
+        h = _bf16(np.maximum(h @ _bf16(W[f"W{i}"]) + b[f"b{i}"], 0.0))
+    return h @ _bf16(W["W4"]) + b["b4"][0]
+
+
+@pytest.mark.parametrize("weights", ["init", "trained"])
+def test_score_kernel_vs_bf16_twin(sp, ctx, weights):
+    """Against a twin that rounds where the kernel rounds, only the order of
+    the fp32 sums differs (and with it, rarely, one activation's bf16
+    rounding), so the scores agree far inside the plain twin's bound; the
+    batch spans many 16-tuple tiles and a ragged last one."""
+    print(f"[gpu-case] pruner score bf16 twin {weights}", flush=True)
+    mesh, R, x3, q0, q3, qt, y = _batch(20000 + 7, 6)
+    dm, dR, d3, t0, t3, tt = _dev(sp, mesh, R, x3, q0, q3, qt)
+    if weights == "init":
+        p = mlp.init_params(7)
+    else:
+        from paper_2405_13409_amd import train_pruner
+
+        p = train_pruner.load().params.cpu().numpy().astype(np.float64)
+    X = mlp.features(mesh.P, mesh.N, mesh.tri, R, x3, q0, q3, qt)
+    z = _forward_bf16(p, X)
+    pref = 1 / (1 + np.exp(-z))
+    params = torch.from_numpy(p.astype(np.float32)).cuda()
+    scores = torch.zeros(len(q0), dtype=torch.float32, device="cuda")
+    ctx.prune_score(dm, dR, d3, t0, t3, tt, params, 0.5, scores=scores)
+    torch.cuda.synchronize()
+    d = np.abs(scores.cpu().numpy() - pref)
+    print("max", d.max(), "median", np.median(d))
+    assert d.max() < 2e-3 and np.median(d) < 1e-5
