@@ -535,6 +535,7 @@ spoly_status ensure_pruner_work(spoly_ctx* ctx, int64_t n)
     size_t odZ4 = take(cap * 16 * bf), odZ = take(cap * spoly::kHid * bf);
     size_t oZ1 = take(cap * spoly::kHid * f4), oZ2 = take(cap * spoly::kHid * f4), oZ3 = take(cap * spoly::kHid * f4);
     size_t oZ4 = take(cap * 16 * f4), odH = take(cap * spoly::kHid * f4);
+    size_t opart = take(size_t(spoly::kGemmSplitMax) * spoly::kHid * spoly::kHid * f4);
     if (hipMalloc(&ctx->pw_block, off) != hipSuccess) { ctx->pw_block = nullptr; return SPOLY_E_DEVICE; }
     char* b = static_cast<char*>(ctx->pw_block);
     spoly::PrunerWork& W = ctx->pw;
@@ -544,6 +545,7 @@ spoly_status ensure_pruner_work(spoly_ctx* ctx, int64_t n)
     W.dZ4 = (unsigned short*)(b + odZ4); W.dZ = (unsigned short*)(b + odZ);
     W.Z1 = (float*)(b + oZ1); W.Z2 = (float*)(b + oZ2); W.Z3 = (float*)(b + oZ3); W.Z4 = (float*)(b + oZ4);
     W.dH = (float*)(b + odH);
+    W.part = (float*)(b + opart);
     return SPOLY_OK;
 }
 

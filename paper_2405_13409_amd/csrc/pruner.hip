@@ -2,11 +2,11 @@
 // (ReLU, sigmoid) scores each (x0, T1, T2, x3) tuple from the separators and
 // the positions / normals of both triangles; tuples scoring below a
 // calibrated threshold are not sent to the solver.  Dense layers run on the
-// matrix cores: bf16 operands, fp32 accumulation (v_mfma_f32_16x16x32_bf16 in
-// the scorer, v_mfma_f32_16x16x16_bf16 in the training GEMM).
+// matrix cores: bf16 operands, fp32 accumulation (v_mfma_f32_16x16x32_bf16;
+// the scorer takes its last 16 inputs in one v_mfma_f32_16x16x16_bf16 step).
 //   training : k_gather -> 4 x (GEMM, bias/ReLU) -> loss gradient -> backward
 //              GEMMs (split-K for weight gradients) -> Adam
-//   inference: one fused kernel, weights staged in LDS, 16 tuples per wave tile.
+//   inference: one fused kernel, weights staged in LDS, two 16-tuple tiles per wave.
 #include <hip/hip_bf16.h>
 
 #include "spoly_dev.hpp"
@@ -57,45 +57,63 @@ __global__ void __launch_bounds__(256) k_gather(PrunerIO io, unsigned short* X, 
 }
 
 // ------------------------------------------------------------------ generic bf16 GEMM on MFMA
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+
 // C(m,n) (+)= sum_k A(m,k) B(k,n), A(m,k) = A[m*sam + k*sak], B(k,n) = B[k*sbk + n*sbn],
 // fp32 C row-major with leading dimension ldc.  64x64 tile per workgroup
-// (2x2 waves of 32x32, each 2x2 MFMA 16x16 tiles), K in steps of 16; blockIdx.z
-// splits K, partial sums are added atomically (C zeroed by the caller).
-// Operand fragments: lane l holds rows/cols (l & 15) and k = 4 (l >> 4) + i.
+// (2x2 waves of 32x32, each 2x2 instructions of 16x16x32), K in steps of 32;
+// blockIdx.z splits K: partial sums go to G.part when it is set (summed in
+// order by k_split_sum), else they are added atomically (C zeroed by the
+// caller).  Each step stages A as [m][k] and B as [n][k] in LDS, read from
+// global memory along whichever index is unit-stride so the loads coalesce;
+// a lane's fragment -- row (lane & 15), eight consecutive k -- is then one
+// 16-byte LDS read.  Rows are padded to 40 bf16 so that the 16 rows a
+// quarter-wave reads start in distinct bank groups.
+constexpr int kGemmLd = 32 + 8;
+
 __global__ void __launch_bounds__(256) k_gemm(GemmArgs G)
 {
+    __shared__ __attribute__((aligned(16))) unsigned short As[64 * kGemmLd], Bs[64 * kGemmLd];
     const int lane = lane_id();
     const int w = threadIdx.x / kWave;
-    const int m0 = blockIdx.y * 64 + (w >> 1) * 32;
-    const int n0 = blockIdx.x * 64 + (w & 1) * 32;
-    const int kchunk = (G.K + gridDim.z - 1) / gridDim.z;
+    const int bm = blockIdx.y * 64, bn = blockIdx.x * 64;
+    const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+    const int kchunk = ((G.K + gridDim.z - 1) / gridDim.z + 31) & ~31;
     const int kbeg = blockIdx.z * kchunk;
     const int kend = min(G.K, kbeg + kchunk);
+    const bool a_kfast = G.sak == 1, b_kfast = G.sbk == 1;
     v4f acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
-    const int r = lane & 15, kq = (lane >> 4) * 4;
-    for (int k0 = kbeg; k0 < kend; k0 += 16) {
-        v4s af[2], bfr[2];
+    const int r = lane & 15, k8 = (lane >> 4) * 8, kq = (lane >> 4) * 4;
+    for (int k0 = kbeg; k0 < kend; k0 += 32) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int e = threadIdx.x + 256 * i;   // 0 .. 64*32-1
+            const int am = a_kfast ? e >> 5 : e & 63, ak = a_kfast ? e & 31 : e >> 6;
+            const int gm = bm + am, gka = k0 + ak;
+            As[am * kGemmLd + ak] =
+                (gm < G.M && gka < kend) ? G.A[int64_t(gm) * G.sam + int64_t(gka) * G.sak] : (unsigned short)0;
+            const int bnn = b_kfast ? e >> 5 : e & 63, bk = b_kfast ? e & 31 : e >> 6;
+            const int gn = bn + bnn, gkb = k0 + bk;
+            Bs[bnn * kGemmLd + bk] =
+                (gn < G.N && gkb < kend) ? G.B[int64_t(gkb) * G.sbk + int64_t(gn) * G.sbn] : (unsigned short)0;
+        }
+        __syncthreads();
+        bf8v af[2], bfr[2];
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
-            const int m = m0 + 16 * t + r;
-            const int n = n0 + 16 * t + r;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int k = k0 + kq + i;
-                const bool kin = k < kend;
-                af[t][i] = (kin && m < G.M) ? (short)G.A[int64_t(m) * G.sam + int64_t(k) * G.sak] : (short)0;
-                bfr[t][i] = (kin && n < G.N) ? (short)G.B[int64_t(k) * G.sbk + int64_t(n) * G.sbn] : (short)0;
-            }
+            af[t] = *reinterpret_cast<const bf8v*>(As + (wm + 16 * t + r) * kGemmLd + k8);
+            bfr[t] = *reinterpret_cast<const bf8v*>(Bs + (wn + 16 * t + r) * kGemmLd + k8);
         }
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int j = 0; j < 2; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[i], bfr[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+        __syncthreads();
     }
     // D fragment: lane holds column (lane & 15), rows 4 (lane >> 4) + i
 #pragma unroll
@@ -104,21 +122,39 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs G)
         for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int m = m0 + 16 * i + kq + e;
-                const int n = n0 + 16 * j + r;
+                const int m = bm + wm + 16 * i + kq + e;
+                const int n = bn + wn + 16 * j + r;
                 if (m < G.M && n < G.N) {
                     float* c = G.C + int64_t(m) * G.ldc + n;
-                    if (gridDim.z > 1) atomicAdd(c, G.alpha * acc[i][j][e]);
+                    if (G.part) G.part[(int64_t(blockIdx.z) * G.M + m) * G.N + n] = acc[i][j][e];
+                    else if (gridDim.z > 1) atomicAdd(c, G.alpha * acc[i][j][e]);
                     else *c = G.alpha * acc[i][j][e] + (G.accumulate ? *c : 0.0f);
                 }
             }
 }
 
+// C = alpha * (sum of the split partials, in split order) (+ C)
+__global__ void k_split_sum(GemmArgs G, int split)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t mn = int64_t(G.M) * G.N;
+    if (i >= mn) return;
+    float acc = 0.0f;
+    for (int z = 0; z < split; ++z) acc += G.part[z * mn + i];
+    float* c = G.C + (i / G.N) * G.ldc + (i % G.N);
+    *c = G.alpha * acc + (G.accumulate ? *c : 0.0f);
+}
+
 hipError_t launch_gemm(const GemmArgs& G, int split_k, hipStream_t stream)
 {
     if (G.M <= 0 || G.N <= 0 || G.K <= 0) return hipSuccess;
-    dim3 grid((G.N + 63) / 64, (G.M + 63) / 64, split_k < 1 ? 1 : split_k);
+    const int split = split_k < 1 ? 1 : split_k;
+    dim3 grid((G.N + 63) / 64, (G.M + 63) / 64, split);
     hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, stream, G);
+    if (G.part) {
+        const int64_t mn = int64_t(G.M) * G.N;
+        hipLaunchKernelGGL(k_split_sum, dim3(unsigned((mn + 255) / 256)), dim3(256), 0, stream, G, split);
+    }
     return hipGetLastError();
 }
 
@@ -211,7 +247,7 @@ __global__ void k_adam(float* p, const float* g, float* m, float* v, int64_t n, 
 }
 
 // ------------------------------------------------------------------ fused inference
-// One 16-tuple tile per wave, activations kept in registers: every layer
+// Two 16-tuple tiles per wave, activations kept in registers: every layer
 // computes H^T = W^T X^T on the matrix cores (weights as the A operand, the
 // tile's activations as B), 32 inputs per instruction.  A 16x16 D fragment
 // leaves lane l with tuple l & 15 and output neurons 4 (l >> 4) .. + 3 of its
@@ -222,19 +258,18 @@ __global__ void k_adam(float* p, const float* g, float* m, float* v, int64_t n, 
 // matter to the sum as long as A and B agree on it, which they do: both take
 // a lane's eight values in the same slots.  Weights and biases sit in LDS,
 // transposed to [out][in] so that a lane's eight k of an A fragment are one
-// 16-byte read; the output layer's row 0 leaves each tuple's logit in lanes
-// 0..15.
+// 16-byte read, which serves both tiles' instructions; the output layer's
+// row 0 leaves each tuple's logit in lanes 0..15.
 // Weight rows are padded by 8 bf16 (16 bytes): with 128 bf16 per row the 16
 // rows a quarter-wave reads at one k offset would sit 256 bytes apart, all in
 // the same LDS banks; padded, the reads of a quarter-wave cover all 64 banks
 // once.
 constexpr int kS1 = kFeat + 8, kS2 = kHid + 8;
 constexpr int kW1 = kHid * kS1, kW2 = kHid * kS2, kW4 = 16 * kS2;
-constexpr int kPruneWaves = 12;
+constexpr int kPruneWaves = 12, kPruneTiles = 2;
 constexpr int kPruneLds = (kW1 + 2 * kW2 + kW4) * 2 + 4 * kHid * 4;
 
 typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
-typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 typedef float f2v __attribute__((ext_vector_type(2)));
 typedef float f8v __attribute__((ext_vector_type(8)));
 
@@ -259,19 +294,42 @@ __device__ __forceinline__ int kperm(int slot)
     return 32 * c + 4 * g + (p & 3) + 16 * (p >> 2);
 }
 
-template <int KC, int NT, int LD>
-__device__ __forceinline__ void layer32(const unsigned short* wt /*[NT*16][LD], LD >= KC*32*/, const bf8v (&x)[KC],
-                                        v4f (&acc)[NT])
+// First-layer input slot -> feature index (-1: zero).  The sum over inputs
+// does not care about their order, so each lane's twelve slots are chosen to
+// be contiguous in memory: slots 8g .. 8g + 7 are floats (g & 1) * 8 .. + 7 of
+// the feature row of T1 (g < 2) or T2 (g >= 2), and slots 32 + 4g .. + 3 are
+// x0/2 (g = 0), the row's last two floats (g = 1: T1, g = 3: T2) or x3/2
+// (g = 2).  A row holds positions/2 (9 floats) then normals (9); features are
+// x0/2, x3/2, T1 positions, T2 positions, T1 normals, T2 normals.
+__device__ __forceinline__ int scorer_feature(int slot)
+{
+    if (slot < 32) {
+        const int g = slot >> 3, e = (g & 1) * 8 + (slot & 7);
+        return e < 9 ? (g < 2 ? 6 : 15) + e : (g < 2 ? 24 : 33) + e - 9;
+    }
+    if (slot >= 48) return -1;
+    const int g = (slot - 32) >> 2, p = slot & 3;
+    if (g == 0 || g == 2) return p < 3 ? (g == 0 ? 0 : 3) + p : -1;
+    return p < 2 ? (g == 1 ? 24 : 33) + 7 + p : -1;
+}
+
+template <int KC, int NT, int LD, int T>
+__device__ __forceinline__ void layer32(const unsigned short* wt /*[NT*16][LD], LD >= KC*32*/,
+                                        const bf8v (&x)[T][KC], v4f (&acc)[T][NT])
 {
     const int lane = lane_id(), r = lane & 15, k8 = (lane >> 4) * 8;
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) acc[nt] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[t][nt] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int c = 0; c < KC; ++c) {
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
             const bf8v w = *reinterpret_cast<const bf8v*>(wt + (nt * 16 + r) * LD + c * 32 + k8);
-            acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, x[c], acc[nt], 0, 0, 0);
+#pragma unroll
+            for (int t = 0; t < T; ++t)
+                acc[t][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, x[t][c], acc[t][nt], 0, 0, 0);
         }
         // keep the weight reads of one k-chunk in flight at a time (the
         // scheduler would otherwise hoist a whole layer's and spill)
@@ -331,8 +389,8 @@ __global__ void __launch_bounds__(kPruneWaves * 64) k_prune_score(PrunerIO io, c
     float* bias = reinterpret_cast<float*>(W4t + kW4);   // b1, b2, b3 [128 each], b4
     const PrunerLayout L;
     for (int i = threadIdx.x; i < kW1; i += blockDim.x) {
-        const int o = i / kS1, k = i % kS1;
-        W1t[i] = k < kIn ? f2bf(params[L.w1 + k * kHid + o]) : (unsigned short)0;
+        const int o = i / kS1, f = scorer_feature(i % kS1);
+        W1t[i] = f >= 0 ? f2bf(params[L.w1 + f * kHid + o]) : (unsigned short)0;
     }
     for (int i = threadIdx.x; i < kW2; i += blockDim.x) {
         const int o = i / kS2, k = i % kS2;
@@ -353,94 +411,89 @@ __global__ void __launch_bounds__(kPruneWaves * 64) k_prune_score(PrunerIO io, c
     __syncthreads();
     const int w = threadIdx.x / kWave, lane = lane_id();
     const int r = lane & 15, g = lane >> 4;
-    const int64_t ntile = (io.n + 15) / 16;
+    constexpr int T = kPruneTiles;
+    const int64_t ngroup = (io.n + 16 * T - 1) / (16 * T);
     const int64_t stride = int64_t(gridDim.x) * kPruneWaves;
-    // Software pipeline over this wave's tiles: the tuple ids of tile i+2 and
-    // the feature rows of tile i+1 are requested before tile i's layers run,
-    // so their latency overlaps the matrix work.
-    struct Ids {
-        int j0, j3, t1, t2;
-        bool ok;
-    };
-    auto load_ids = [&](int64_t tile) {
-        Ids d{0, 0, 0, 0, false};
-        const int64_t q = tile * 16 + r;
-        if (tile < ntile && q < io.n) {
-            d.j0 = io.q_x0[q];
-            d.j3 = io.q_x3[q];
-            d.t1 = io.q_tris[2 * q];
-            d.t2 = io.q_tris[2 * q + 1];
-            d.ok = true;
-        }
-        return d;
-    };
-    // the lane's twelve features of its tuple -- 8g .. 8g + 7 for the 32-wide
-    // chunk, 32 + 4g .. + 3 for the 16-wide one -- out of x0/2, x3/2, T1
-    // positions, T2 positions, T1 normals, T2 normals (zero past the 42nd)
-    auto load_feats = [&](const Ids& d, float (&f)[12]) {
+    // the lane's twelve first-layer inputs of tuple q, in scorer_feature's
+    // slots: eight floats of a triangle's feature row (two 16-byte loads),
+    // then the endpoint or the row's last two floats
+    auto load_feats = [&](int64_t q, float (&f)[12]) {
 #pragma unroll
-        for (int k = 0; k < 12; ++k) {
-            const int fi = k < 8 ? 8 * g + k : 32 + 4 * g + (k - 8);
-            float val = 0.0f;
-            if (d.ok) {
-                if (fi < 3) val = float((fi == 0 ? io.x0x[d.j0] : fi == 1 ? io.x0y[d.j0] : io.x0z[d.j0]) * 0.5);
-                else if (fi < 6) val = float((fi == 3 ? io.x3x[d.j3] : fi == 4 ? io.x3y[d.j3] : io.x3z[d.j3]) * 0.5);
-                else if (fi < kIn) {
-                    const int g = (fi - 6) / 9, rem = (fi - 6) % 9;
-                    const int tt = (g == 0 || g == 2) ? d.t1 : d.t2;
-                    val = tf[size_t(tt) * kTriFeat + (g >= 2 ? 9 : 0) + rem];
-                }
-            }
-            f[k] = val;
+        for (int k = 0; k < 12; ++k) f[k] = 0.0f;
+        if (q >= io.n) return;
+        const int tri = io.q_tris[2 * q + (g >> 1)];
+        const float* row = tf + size_t(tri) * kTriFeat + (g & 1) * 8;
+        const float4 a = *reinterpret_cast<const float4*>(row);
+        const float4 b = *reinterpret_cast<const float4*>(row + 4);
+        f[0] = a.x; f[1] = a.y; f[2] = a.z; f[3] = a.w;
+        f[4] = b.x; f[5] = b.y; f[6] = b.z; f[7] = b.w;
+        if (g & 1) {
+            const float2 c = *reinterpret_cast<const float2*>(row + 8);
+            f[8] = c.x;
+            f[9] = c.y;
+        } else {
+            const int j = g == 0 ? io.q_x0[q] : io.q_x3[q];
+            const double* px = g == 0 ? io.x0x : io.x3x;
+            const double* py = g == 0 ? io.x0y : io.x3y;
+            const double* pz = g == 0 ? io.x0z : io.x3z;
+            f[8] = float(px[j] * 0.5);
+            f[9] = float(py[j] * 0.5);
+            f[10] = float(pz[j] * 0.5);
         }
     };
-    int64_t tile = int64_t(blockIdx.x) * kPruneWaves + w;
-    float f[12];
-    load_feats(load_ids(tile), f);
-    Ids next = load_ids(tile + stride);
-    for (; tile < ntile; tile += stride) {
-        const int64_t q = tile * 16 + r;
-        const bool ok = q < io.n;
-        float fn[12];
-        load_feats(next, fn);
-        next = load_ids(tile + 2 * stride);
+    for (int64_t grp = int64_t(blockIdx.x) * kPruneWaves + w; grp < ngroup; grp += stride) {
+        const int64_t q0 = grp * 16 * T + r;
         // first layer: inputs 0..31 in one 32-wide step, 32..47 in a 16-wide one
-        const bf8v x1a[1] = {__builtin_convertvector(((f8v){f[0], f[1], f[2], f[3], f[4], f[5], f[6], f[7]}), bf8v)};
-        const v4s x1b = frag4(f[8], f[9], f[10], f[11]);
-        v4f acc[8];
-        layer32<1, 8, kS1>(W1t, x1a, acc);
+        bf8v x1a[T][1];
+        v4s x1b[T];
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            float f[12];
+            load_feats(q0 + 16 * t, f);
+            x1a[t][0] = __builtin_convertvector(((f8v){f[0], f[1], f[2], f[3], f[4], f[5], f[6], f[7]}), bf8v);
+            x1b[t] = frag4(f[8], f[9], f[10], f[11]);
+        }
+        v4f acc[T][8];
+        layer32<1, 8, kS1, T>(W1t, x1a, acc);
 #pragma unroll
         for (int nt = 0; nt < 8; ++nt) {
-            const v4s w = *reinterpret_cast<const v4s*>(W1t + (nt * 16 + r) * kS1 + 32 + 4 * g);
-            acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w, x1b, acc[nt], 0, 0, 0);
+            const v4s wv = *reinterpret_cast<const v4s*>(W1t + (nt * 16 + r) * kS1 + 32 + 4 * g);
+#pragma unroll
+            for (int t = 0; t < T; ++t)
+                acc[t][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wv, x1b[t], acc[t][nt], 0, 0, 0);
         }
-        bf8v x[4];
-        relu_frags(acc, bias, x);
-        layer32<4, 8, kS2>(W2t, x, acc);
-        relu_frags(acc, bias + kHid, x);
-        layer32<4, 8, kS2>(W3t, x, acc);
-        relu_frags(acc, bias + 2 * kHid, x);
-        v4f out[1];
-        layer32<4, 1, kS2>(W4t, x, out);
-        // lanes 0..15: row 0 of the output tile, the logit of tuple r
-        const float zr = out[0][0] + bias[3 * kHid];
-        const bool mine = lane < 16 && ok;
-        const float p = 1.0f / (1.0f + expf(-zr));
-        if (mine && scores) scores[q] = p;
-        const bool keep = mine && p >= threshold;
-        const unsigned long long bal = __ballot(keep);
-        const int tot = __popcll(bal);
-        if (tot > 0) {
-            unsigned long long base = 0;
-            if (lane == 0) base = atomicAdd(keep_count, (unsigned long long)tot);
-            base = __shfl(base, 0, kWave);
-            if (keep) {
-                const unsigned long long o = base + __popcll(bal & ((1ull << lane) - 1ull));
-                if (o < (unsigned long long)cap) keep_idx[o] = int32_t(q);
+        bf8v x[T][4];
+#pragma unroll
+        for (int t = 0; t < T; ++t) relu_frags(acc[t], bias, x[t]);
+        layer32<4, 8, kS2, T>(W2t, x, acc);
+#pragma unroll
+        for (int t = 0; t < T; ++t) relu_frags(acc[t], bias + kHid, x[t]);
+        layer32<4, 8, kS2, T>(W3t, x, acc);
+#pragma unroll
+        for (int t = 0; t < T; ++t) relu_frags(acc[t], bias + 2 * kHid, x[t]);
+        v4f out[T][1];
+        layer32<4, 1, kS2, T>(W4t, x, out);
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            // lanes 0..15: row 0 of the output tile, the logit of tuple q
+            const int64_t q = q0 + 16 * t;
+            const float zr = out[t][0][0] + bias[3 * kHid];
+            const bool mine = lane < 16 && q < io.n;
+            const float p = 1.0f / (1.0f + expf(-zr));
+            if (mine && scores) scores[q] = p;
+            const bool keep = mine && p >= threshold;
+            const unsigned long long bal = __ballot(keep);
+            const int tot = __popcll(bal);
+            if (tot > 0) {
+                unsigned long long base = 0;
+                if (lane == 0) base = atomicAdd(keep_count, (unsigned long long)tot);
+                base = __shfl(base, 0, kWave);
+                if (keep) {
+                    const unsigned long long o = base + __popcll(bal & ((1ull << lane) - 1ull));
+                    if (o < (unsigned long long)cap) keep_idx[o] = int32_t(q);
+                }
             }
         }
-#pragma unroll
-        for (int k = 0; k < 12; ++k) f[k] = fn[k];
     }
 }
 
@@ -466,13 +519,13 @@ hipError_t launch_prune_score(const PrunerIO& io, const float* params, float thr
     }
     k_tri_feat<<<nblk(n_tris, 256), 256, 0, s>>>(io, n_tris, tri_feat);
     // persistent: one block per compute unit (its LDS allows no second), each
-    // loading the weights once and striding over 16-tuple tiles
+    // loading the weights once and striding over pairs of 16-tuple tiles
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
         cus = 256;
-    const int64_t tiles = (io.n + 15) / 16;
-    int64_t blocks = (tiles + kPruneWaves - 1) / kPruneWaves;
+    const int64_t groups = (io.n + 16 * kPruneTiles - 1) / (16 * kPruneTiles);
+    int64_t blocks = (groups + kPruneWaves - 1) / kPruneWaves;
     if (blocks > cus) blocks = cus;
     hipLaunchKernelGGL(k_prune_score, dim3(unsigned(blocks)), dim3(kPruneWaves * 64), kPruneLds, s, io, tri_feat,
                        params, threshold, scores, keep_idx, cap, keep_count);
@@ -493,7 +546,10 @@ hipError_t pruner_fwd_bwd(const PrunerIO& io, const float* labels, float pos_w, 
     hipError_t first_err = hipSuccess;
     auto gemm = [&](const unsigned short* A, int64_t sam, int64_t sak, const unsigned short* B, int64_t sbk,
                     int64_t sbn, float* C, int ldc, int M, int N, int K, int split) {
-        GemmArgs G{A, sam, sak, B, sbk, sbn, C, ldc, M, N, K, 1.0f, 0};
+        // weight gradients (M, N <= 128, K = batch): deterministic split-K
+        // through the partials buffer so that the launch fills the chip
+        const bool wgrad = split > 1;
+        GemmArgs G{A, sam, sak, B, sbk, sbn, C, ldc, M, N, K, 1.0f, 0, wgrad ? W.part : nullptr};
         const hipError_t r = launch_gemm(G, split, s);
         if (r != hipSuccess && first_err == hipSuccess) first_err = r;
     };
@@ -510,7 +566,8 @@ hipError_t pruner_fwd_bwd(const PrunerIO& io, const float* labels, float pos_w, 
                        1.0f / float(n), W.dZ4, (float*)nullptr, loss);
     // backward
     hipLaunchKernelGGL(k_fill, dim3(nblk(kNParams, 256)), dim3(256), 0, s, grads, int64_t(kNParams), 0.0f);
-    const int split = 1;   // no atomics: the gradients, hence training, are deterministic
+    // no atomics: the gradients, hence training, are deterministic
+    const int split = int(std::max<int64_t>(1, std::min<int64_t>(kGemmSplitMax, n / 512)));
     // dW4 = H3^T dZ4 : A(m=in, k=row) = H3[row*128 + m], B(k=row, n=0) = dZ4[row*16]
     gemm(W.H3, 1, kHid, W.dZ4, 16, 1, grads + L.w4, 1, kHid, 1, nn, split);
     hipLaunchKernelGGL(k_colsum, dim3(1), dim3(256), 0, s, W.dZ4, n, 1, 16, grads + L.b4);

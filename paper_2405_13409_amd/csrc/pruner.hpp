@@ -40,12 +40,17 @@ struct GemmArgs {
     int M, N, K;
     float alpha;
     int accumulate;
+    // split-K without atomics: with part set, split k writes its [M x N]
+    // partial tile to part + k*M*N and a second kernel adds them in k order
+    float* part;
 };
+constexpr int kGemmSplitMax = 128;
 
 struct PrunerWork {   // per-batch activations (device), sized for `cap` tuples
     int64_t cap;
     unsigned short *X, *Pb, *H1, *H2, *H3, *dZ4, *dZ;
     float *Z1, *Z2, *Z3, *Z4, *dH;
+    float* part;   // kGemmSplitMax x kHid x kHid split-K partials
 };
 
 hipError_t launch_gemm(const GemmArgs& G, int split_k, hipStream_t stream);
