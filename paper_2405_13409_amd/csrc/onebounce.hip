@@ -262,7 +262,10 @@ __device__ __forceinline__ bool polish(const Geo& g, double eta0, double eta1, i
         u -= du;
         v -= dv;
         step = fabs(du) + fabs(dv);
-        if (!(step > 1e-16)) break;
+        // Newton converges quadratically at a simple solution: after a step
+        // below 1e-13 the error left is far below FP64 rounding, and further
+        // steps only move within the rounding of the residual.
+        if (!(step > 1e-13)) break;
     }
     return step <= 1e-10;
 }
