@@ -166,13 +166,15 @@ def main():
         cap_s[ev] = int(len(sols) * 1.2) + 1024
         del q0, q2, qt
     buf = {}
-    for ev, _, _ in events:
+    # candidate counts of both events, then solution counts: one fill per step, one read of each pair
+    counts = torch.zeros(2 * len(events), dtype=torch.int64, device="cuda")
+    for i, (ev, _, _) in enumerate(events):
         buf[ev] = dict(q0=torch.empty(cap_c[ev], dtype=torch.int32, device="cuda"),
                        q2=torch.empty(cap_c[ev], dtype=torch.int32, device="cuda"),
                        qt=torch.empty(cap_c[ev], dtype=torch.int32, device="cuda"),
-                       ccount=torch.zeros(1, dtype=torch.int64, device="cuda"),
+                       ccount=counts[i:i + 1],
                        out=torch.empty(cap_s[ev] * spoly.SOLUTION_DTYPE.itemsize, dtype=torch.uint8, device="cuda"),
-                       scount=torch.zeros(1, dtype=torch.int64, device="cuda"))
+                       scount=counts[len(events) + i:len(events) + i + 1])
     prm = spoly.default_params()
     prm.flags = spoly.SPOLY_FLAG_STAGE_TIMES
     stream = torch.cuda.current_stream()
@@ -183,16 +185,20 @@ def main():
     n_cand = {}
 
     def step(record: bool):
+        # both culls, one read of their counts (the solve takes its count from the host), both solves
         tot_inst, tot_sol = 0, 0
+        counts.zero_()
         for ev, e0, e1 in events:
             b = buf[ev]
-            h = ctxs[ev].h
-            b["ccount"].zero_()
-            b["scount"].zero_()
-            st = L.spoly_cull_1bounce(h, ctypes.byref(dm.c), ctypes.byref(pts[ev].c), ctypes.byref(dl.c), e0, e1,
-                                      1e-3, p(b["q0"]), p(b["q2"]), p(b["qt"]), cap_c[ev], p(b["ccount"]), sptr)
+            st = L.spoly_cull_1bounce(ctxs[ev].h, ctypes.byref(dm.c), ctypes.byref(pts[ev].c), ctypes.byref(dl.c),
+                                      e0, e1, 1e-3, p(b["q0"]), p(b["q2"]), p(b["qt"]), cap_c[ev], p(b["ccount"]),
+                                      sptr)
             assert st == 0
-            nq = int(b["ccount"].item())
+        nqs = counts[: len(events)].tolist()
+        for i, (ev, e0, e1) in enumerate(events):
+            b = buf[ev]
+            h = ctxs[ev].h
+            nq = int(nqs[i])
             assert nq <= cap_c[ev]
             e_a = torch.cuda.Event(enable_timing=True)
             e_b = torch.cuda.Event(enable_timing=True)
@@ -206,9 +212,9 @@ def main():
                 solve_ms[ev].append((e_a, e_b))
             n_cand[ev] = nq
             tot_inst += nq
-        torch.cuda.synchronize()
-        for ev, _, _ in events:
-            ns = int(buf[ev]["scount"].item())
+        nss = counts[len(events):].tolist()
+        for i, (ev, _, _) in enumerate(events):
+            ns = int(nss[i])
             assert ns <= cap_s[ev]
             tot_sol += ns
             if record:
