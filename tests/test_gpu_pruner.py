@@ -132,14 +132,14 @@ def _forward_bf16(p, X):
     return h @ _bf16(W["W4"]) + b["b4"][0]
 
 
-@pytest.mark.parametrize("weights", ["init", "trained"])
-def test_score_kernel_vs_bf16_twin(sp, ctx, weights):
+@pytest.mark.parametrize("weights,n", [("init", 20007), ("trained", 20007), ("init", 5)])
+def test_score_kernel_vs_bf16_twin(sp, ctx, weights, n):
     """Against a twin that rounds where the kernel rounds, only the order of
     the fp32 sums differs (and with it, rarely, one activation's bf16
     rounding), so the scores agree far inside the plain twin's bound; the
     batch spans many 16-tuple tiles and a ragged last one."""
-    print(f"[gpu-case] pruner score bf16 twin {weights}", flush=True)
-    mesh, R, x3, q0, q3, qt, y = _batch(20000 + 7, 6)
+    print(f"[gpu-case] pruner score bf16 twin {weights} n={n}", flush=True)
+    mesh, R, x3, q0, q3, qt, y = _batch(n, 6)
     dm, dR, d3, t0, t3, tt = _dev(sp, mesh, R, x3, q0, q3, qt)
     if weights == "init":
         p = mlp.init_params(7)
@@ -157,3 +157,34 @@ def test_score_kernel_vs_bf16_twin(sp, ctx, weights):
     d = np.abs(scores.cpu().numpy() - pref)
     print("max", d.max(), "median", np.median(d))
     assert d.max() < 2e-3 and np.median(d) < 1e-5
+
+
+def test_weight_gradients_repeat_bitwise(sp, ctx):
+    """The weight gradients of a large batch are summed over up to 128 split-K
+    partial tiles in a fixed order, without atomics: two passes give the same
+    bits, and the result still agrees with the FP64 twin.  The reported loss
+    is summed with atomics, so it agrees only to rounding."""
+    n = 65536
+    print(f"[gpu-case] pruner split-K repeat n={n}", flush=True)
+    mesh, R, x3, q0, q3, qt, y = _batch(n, 8)
+    dm, dR, d3, t0, t3, tt = _dev(sp, mesh, R, x3, q0, q3, qt)
+    p = mlp.init_params(9)
+    params = torch.from_numpy(p.astype(np.float32)).cuda()
+    yt = torch.from_numpy(y).cuda()
+    out = []
+    for _ in range(2):
+        grads = torch.zeros_like(params)
+        loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+        ctx.pruner_fwd_bwd(dm, dR, d3, t0, t3, tt, yt, 5.0, params, grads, loss)
+        torch.cuda.synchronize()
+        out.append((grads.cpu().numpy(), float(loss.item())))
+    assert out[0][0].tobytes() == out[1][0].tobytes()
+    assert abs(out[0][1] - out[1][1]) <= 1e-5 * abs(out[0][1])
+    X = mlp.features(mesh.P, mesh.N, mesh.tri, R, x3, q0, q3, qt)
+    bf = lambda a: torch.from_numpy(a.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()  # noqa: E731
+    _, g_ref = mlp.loss_and_grad(p, bf(X), y.astype(np.float64), 5.0)
+    G, Gr = mlp.unpack(out[0][0].astype(np.float64)), mlp.unpack(g_ref)
+    for name in ("W1", "W2", "W3", "W4"):
+        a, b = G[name].ravel(), Gr[name].ravel()
+        rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+        assert rel <= 2e-2, (name, rel)
