@@ -972,14 +972,35 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
 }
 
 // Back: persistent blocks stride over the item list, one candidate per lane.
+// The next item's record (query, root count, roots) is loaded one iteration
+// ahead, so that its latency overlaps this item's work and only the geometry
+// gathers that depend on it remain on the critical path.
 template <int EV>
 __global__ void __launch_bounds__(256) k_ob_back(OneBounceArgs A)
 {
+    static_assert(kObEmit == 2, "the record carried ahead holds two roots");
     __shared__ unsigned long long s_slots[kMaxBlockWaves + 1];
     const int64_t n_items = int64_t(*A.items_count);
-    for (int64_t b0 = int64_t(blockIdx.x) * blockDim.x; b0 < n_items; b0 += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    int64_t qn = 0;
+    int nrn = 0;
+    double vn0 = 0.0, vn1 = 0.0;
+    auto load_item = [&](int64_t i) {
+        if (i < n_items) {
+            qn = A.items_q[i];
+            nrn = A.items_n[i];
+            vn0 = A.items_v[kObEmit * i];
+            vn1 = A.items_v[kObEmit * i + 1];
+        }
+    };
+    load_item(int64_t(blockIdx.x) * blockDim.x + threadIdx.x);
+    for (int64_t b0 = int64_t(blockIdx.x) * blockDim.x; b0 < n_items; b0 += stride) {
         const int64_t i = b0 + threadIdx.x;
         const bool active = i < n_items;
+        const int64_t qc = qn;
+        const int nr = nrn;
+        const double v0 = vn0, v1 = vn1;
+        load_item(i + stride);
         LaneSols S;
         S.n = 0;
         S.over = 0;
@@ -987,8 +1008,7 @@ __global__ void __launch_bounds__(256) k_ob_back(OneBounceArgs A)
         bool swapped = false, defer = false;
         int64_t q = 0;
         if (active) {
-            q = A.items_q[i];
-            const int nr = A.items_n[i];
+            q = qc;
             Geo g;
             tid = setup_geo<EV>(A, q, g);
             swapped = g.swapped;
@@ -996,11 +1016,11 @@ __global__ void __launch_bounds__(256) k_ob_back(OneBounceArgs A)
             if (g.flat) {
                 const P2<double, 1> a64 = a_fp64<0>(g);
                 for (int j = 0; j < nr && ok; ++j)
-                    ok = back_root<EV, 0, true>(g, A, a64, A.items_v[kObEmit * i + j], S, ncand);
+                    ok = back_root<EV, 0, true>(g, A, a64, j == 0 ? v0 : v1, S, ncand);
             } else {
                 const P2<double, 2> a64 = a_fp64<1>(g);
                 for (int j = 0; j < nr && ok; ++j)
-                    ok = back_root<EV, 1, true>(g, A, a64, A.items_v[kObEmit * i + j], S, ncand);
+                    ok = back_root<EV, 1, true>(g, A, a64, j == 0 ? v0 : v1, S, ncand);
             }
             if (!ok) {
                 // An FP32 root whose u misses the triangle narrowly: the whole
