@@ -50,14 +50,14 @@ PRUNER_FLOP = 2 * (42 * 128 + 2 * 128 * 128 + 128)   # multiply-adds of the four
 # ONE_VERTEX_SOURCES, the cull included: it sets the order of the candidates); otherwise traffic is null.
 ONE_VERTEX_SOURCES = ("onebounce.hip", "spoly_dev.hpp", "laplace_gen.inc", "onebounce.hpp", "cull.hip")
 TWO_VERTEX_SOURCES = ("twobounce.hip", "twobounce.hpp", "spoly_dev.hpp")
-TRAFFIC_FRONT = {"sha": "6773c2c05da5c689", "candidates": 99118956, "fetch_kib": 683691.8, "write_kib": 1900960.6,
+TRAFFIC_FRONT = {"sha": "1957ee0810a6953e", "candidates": 99118956, "fetch_kib": 682529.5, "write_kib": 1893897.6,
                  "fetch_scale": 262144.0 / 131083.5, "write_scale": 262144.0 / 262144.0}
 # VALU wave-instructions (rocprofv3 --pmc SQ_INSTS_VALU) per launch of each one-vertex kernel on the glints
 # workload, and per tuple of the two-vertex solve on the RR and TT legs, each group under the source check of
 # its own kernels (profiles/valu_counters.md).
-VALU_INSTS = {"sha": "6773c2c05da5c689",
-              "k_ob_front_R": 2.917e9, "k_ob_back_R": 4.356e8, "k_ob_full_R": 3.706e7,
-              "k_ob_coef_T": 6.219e8, "k_ob_iso_T": 1.691e8, "k_ob_back_T": 9.516e7}
+VALU_INSTS = {"sha": "1957ee0810a6953e",
+              "k_ob_front_R": 2.917e9, "k_ob_back_R": 4.388e8, "k_ob_full_R": 3.702e7,
+              "k_ob_coef_T": 6.219e8, "k_ob_iso_T": 1.691e8, "k_ob_back_T": 9.559e7}
 VALU_INSTS_TT = {"sha": "3f62131393a90e82",
                  "k_tt_solve_RR_per_tuple": 7.352e11 / 9256723, "k_tt_solve_TT_per_tuple": 4.033e11 / 6477601}
 
