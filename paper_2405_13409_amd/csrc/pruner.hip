@@ -149,6 +149,8 @@ hipError_t launch_gemm(const GemmArgs& G, int split_k, hipStream_t stream)
 {
     if (G.M <= 0 || G.N <= 0 || G.K <= 0) return hipSuccess;
     const int split = split_k < 1 ? 1 : split_k;
+    // the partials buffer holds kGemmSplitMax tiles of at most kHid x kHid
+    if (G.part && (split > kGemmSplitMax || int64_t(G.M) * G.N > int64_t(kHid) * kHid)) return hipErrorInvalidValue;
     dim3 grid((G.N + 63) / 64, (G.M + 63) / 64, split);
     hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, stream, G);
     if (G.part) {
